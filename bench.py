@@ -1,0 +1,171 @@
+"""Benchmark of the MPMC hard-disk sampler on one MI355X.
+
+Workload: N = 1024^2 disks at eta = 0.716 (the paper-scale system, Sec. IV),
+triangular start, one trial per non-empty active cell, step tuned during
+warm-up to about 30 % acceptance and then frozen.  One benchmark step is one
+pass of the whole plain hot path over the box: `--sweeps` MPMC sweeps (random
+grid shift + re-bin + four colour sub-sweeps each, replayed from a captured
+HIP graph), then one contact-histogram accumulation (pressure, Sec. II.C.1)
+and one psi_6 field evaluation (Eq. (8)), as logged every 100 sweeps.
+
+Prints one JSON line: whole-job trial moves per second with the state resident
+in HBM, the sweep kernel's roofline figures measured with HIP events on the
+stream it runs on, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+N_DISKS = 1024 * 1024
+ETA = 0.716
+
+
+def algorithmic_bytes_per_sweep(N, M):
+    """What one sweep must move at least: every position read and written
+    (2 x 8 B per disk), every tag read and written (2 x 4 B per disk), every
+    cell count read and written (2 x 1 B per cell)."""
+    return 16 * N + 8 * N + 2 * M * M
+
+
+def tune_step(box, target=0.30, rounds=6, block=100):
+    """Equilibration-only step tuning: m <- round(m * acc / target)."""
+    m = box.info()["step_m"]
+    acc = None
+    for _ in range(rounds):
+        t, a = box.sweep(block, counts=True)
+        acc = a / t
+        new = max(1, min(255, int(round(m * acc / target))))
+        if new == m:
+            break
+        m = new
+        box.set_step(m)
+    return m, acc
+
+
+def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
+    """The oracle (single thread) on the same start and step: sweeps of the
+    full 1024^2 box until about target_seconds of CPU work."""
+    from oracle.orc import OracleBox
+    o = OracleBox(N_DISKS, ETA, seed=seed, lattice=1, step_m=step_m)
+    t0 = time.perf_counter()
+    o.sweep(1)
+    one = time.perf_counter() - t0
+    k = max(1, int(target_seconds / max(one, 1e-3)) - 1)
+    i0 = o.info()
+    t0 = time.perf_counter()
+    o.sweep(k)
+    dt = time.perf_counter() - t0
+    i1 = o.info()
+    return dict(value=(i1["trials"] - i0["trials"]) / dt, unit="trial moves/s", cores=1,
+                kind="oracle",
+                sample="%d sweeps of the N=1024^2 eta=0.716 box after 1 from the same "
+                       "triangular start (%.1f s, 1 thread, %s)" % (k, dt, platform.processor() or
+                                                                     platform.machine()))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sweeps", type=int, default=100, help="sweeps per benchmark step")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sampler runs one box per GPU and this build "
+              "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular",
+                     stream=stream.cuda_stream)
+        box.set_graphs(args.sweeps)  # one captured graph per benchmark step
+        step_m, acc0 = tune_step(box)
+        info = box.info()
+        for _ in range(args.warmup):
+            box.sweep(args.sweeps)
+            box.accumulate_contacts()
+            box.psi6_field(device=True)
+        box.reset_contacts()
+        torch.cuda.synchronize()
+
+        t_before = box.info()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        psi_series = []
+        for s in range(args.steps):
+            ev[s][0].record(stream)
+            box.sweep(args.sweeps)
+            ev[s][1].record(stream)
+            box.accumulate_contacts()
+            _, _, Psi = box.psi6_field(device=True)
+            psi_series.append(Psi)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        t_after = box.info()
+
+    trials = t_after["trials"] - t_before["trials"]
+    accepts = t_after["accepts"] - t_before["accepts"]
+    sweep_ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * args.sweeps)
+    bytes_per = algorithmic_bytes_per_sweep(info["N"], info["M"])
+    achieved = bytes_per / (sweep_ms * 1e-3) / 1e9
+    pressure = box.measure_pressure()
+    overlaps, bad = box.validate()
+
+    line = {
+        "metric": "trial moves/s and psi6-decorrelation sweeps/s, 1024^2 disks eta=0.716",
+        "value": trials / elapsed,
+        "unit": "trial moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (triangular-lattice start, Philox4x32-10 seed %d)" % args.seed,
+        "config": {"workload": "plain MPMC, N=1024^2 hard disks, eta=0.716, triangular start, "
+                               "1 trial per non-empty active cell, step tuned to ~30%% "
+                               "acceptance (m=%d, d=%.4f sigma); step = %d sweeps + contact "
+                               "histogram + psi6 field" % (step_m, step_m / 256.0, args.sweeps),
+                   "N": info["N"], "eta": ETA, "eta_eff": info["eta_eff"], "M": info["M"],
+                   "w": info["w"], "n_trial": info["n_trial"], "step_m": step_m,
+                   "sweeps_per_step": args.sweeps, "schedule": "fused" if info["schedule"] == 2
+                   else "simple", "tile": info["tile"]},
+        "sweeps_per_s": args.steps * args.sweeps / elapsed,
+        "sweep_us": sweep_ms * 1e3,
+        "acceptance": accepts / max(trials, 1),
+        "trials_per_sweep": trials / (args.steps * args.sweeps),
+        "psi6_decorrelations_per_s": None,
+        "P_star_sample": pressure["P_star"],
+        "abs_Psi6_mean": sum(abs(p) for p in psi_series) / len(psi_series),
+        "validate": {"overlaps": overlaps, "bad": bad},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_fused (one sweep per launch)",
+                     "algorithmic_bytes_per_launch": bytes_per},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(0, args.seed, step_m)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

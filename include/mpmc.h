@@ -1,0 +1,216 @@
+/*
+ * mpmc.h — C ABI of the MI355X massively parallel local Monte Carlo (MPMC)
+ * sampler for hard disks (Engel, Anderson, Glotzer, Isobe, Bernard, Krauth,
+ * "Hard-disk equation of state: first-order liquid-hexatic transition in two
+ * dimensions with three simulation methods", arXiv:1211.1645).
+ *
+ * Model (Sec. II.A): N hard disks of radius sigma = 1 in a periodic L x L
+ * square box at packing fraction eta = N pi / L^2, sampled in the NVT
+ * ensemble.  Sampler (Sec. II.B): a four-colour checkerboard of cells of
+ * width w >= 2 sigma, shifted at random every sweep; all cells of one colour
+ * make local trial moves at once, rejecting moves that leave the cell or
+ * overlap another disk.  Observables: the contact pair histogram and the
+ * pressure from the contact value of g(r) (Sec. II.C.1, Eqs. (1), (2), (4)),
+ * and the orientational order psi_j, Psi_6 (Eq. (8), Sec. III).
+ *
+ * Conventions for every entry point:
+ *  - Return value: MPMC_OK (0) or a negative MPMC_E* code; the message of the
+ *    last failure on the calling thread is mpmc_last_error().  No C++
+ *    exception crosses this interface.  After MPMC_EDEVICE a handle may only
+ *    be freed.
+ *  - Ownership: a box handle owns all its device state; buffers passed in are
+ *    owned by the caller and only read or written during the call.
+ *  - Pointers are host pointers unless a parameter says "device".
+ *  - Work is enqueued on the box's stream (mpmc_params.stream, a hipStream_t;
+ *    NULL = the default stream).  Calls that return host data synchronise
+ *    that stream before returning.
+ *  - Units: sigma = 1.  Positions are on the lattice of spacing q = 2^-22; a
+ *    "q unit" is one lattice step.  Coordinates inside a cell are fp32.
+ */
+#ifndef MPMC_H
+#define MPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPMC_OK 0
+#define MPMC_EINVAL (-1)    /* invalid argument or parameter combination */
+#define MPMC_ENOMEM (-2)    /* device or host allocation failed */
+#define MPMC_EDEVICE (-3)   /* HIP runtime error; the handle may only be freed */
+#define MPMC_ESTATE (-4)    /* call not valid in the current state */
+#define MPMC_EOVERFLOW (-5) /* a cell exceeded its capacity (corrupt input) */
+#define MPMC_EIO (-6)       /* checkpoint file error */
+
+#define MPMC_LATTICE_SQUARE 0     /* sqrt(N) x sqrt(N) square lattice */
+#define MPMC_LATTICE_TRIANGULAR 1 /* sqrt(N) rows, odd rows offset by half */
+#define MPMC_LATTICE_NONE 2       /* no start; call mpmc_set_positions */
+
+#define MPMC_SCHED_AUTO 0   /* fused tile kernel, autotuned tile */
+#define MPMC_SCHED_SIMPLE 1 /* one kernel per colour sub-sweep */
+#define MPMC_SCHED_FUSED 2  /* one LDS-tiled kernel per sweep, tile given */
+
+typedef struct mpmc_box_s *mpmc_box;
+
+typedef void *(*mpmc_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*mpmc_free_fn)(void *ptr, void *ctx);
+
+typedef struct mpmc_params {
+    uint32_t step_m;    /* trial step d = step_m * 2^-8 sigma, 1..255; each
+                           axis of a displacement is uniform over 2^14 odd
+                           multiples of step_m q inside (-d, d) */
+    uint32_t n_trial;   /* trials per non-empty active cell and sweep, >= 1
+                           ("fixed independent of cell occupancy", Sec. II.B) */
+    int32_t lattice;    /* MPMC_LATTICE_* start */
+    double cell_min;    /* minimum cell width in sigma (>= 2, Sec. II.B) */
+    double hist_dr;     /* contact histogram bin width (Sec. II.C.1: 1e-3) */
+    uint32_t hist_bins; /* bins from r = 2 sigma (Sec. II.C.1: 100 -> 2.1) */
+    uint32_t fit_order; /* polynomial order of the contact fit (Sec. II.C.1: 4) */
+    uint32_t hist_block;/* configurations per block for the pressure standard
+                           error; 0 = no blocking (se = NaN) */
+    uint32_t schedule;  /* MPMC_SCHED_* (the trajectory does not depend on it) */
+    uint32_t tile;      /* fused-kernel tile side in cells; 0 = autotune */
+    void *stream;       /* hipStream_t for all work of the box */
+    mpmc_alloc_fn alloc;/* optional device allocator (both or neither) */
+    mpmc_free_fn free;
+    void *alloc_ctx;
+} mpmc_params;
+
+typedef struct mpmc_info {
+    uint32_t N, M, cap, n_trial, step_m, tile, schedule, hist_bins;
+    int64_t W;          /* cell width in q units */
+    double L;           /* nominal sqrt(N pi / eta) */
+    double L_eff;       /* M w, the simulated box side */
+    double w, eta, eta_eff, hist_dr;
+    uint64_t sweep;     /* sweeps done */
+    int64_t Sx, Sy;     /* accumulated grid shift, q units, mod M W */
+    uint64_t trials, accepts; /* counted since creation */
+    uint64_t n_conf;    /* configurations in the contact histogram */
+} mpmc_info;
+
+/* Fills *p with defaults: step_m 26 (d = 0.1015625), n_trial 1, triangular
+ * start, cell_min 2, hist_dr 1e-3, hist_bins 100, fit_order 4, hist_block 0,
+ * schedule AUTO, tile 0, stream NULL, no allocator.  MPMC_EINVAL if p NULL. */
+int mpmc_default_params(mpmc_params *p);
+
+/* Creates a box of N disks at packing fraction eta with Philox key `seed`.
+ * Geometry: L = sqrt(N pi / eta); M = largest even integer <= L / cell_min
+ * (>= 4 required); w = nearest multiple of q to L / M; the simulated box is
+ * M w (eta_eff in mpmc_info).  p == NULL means defaults.  The lattice starts
+ * need N a perfect square and place row b, column a at
+ * X = floor((2a + 1 + [triangular and b odd]) M W / (2 sqrt N)) mod M W,
+ * Y = floor((2b + 1) M W / (2 sqrt N)), tag b sqrt(N) + a.
+ * Errors: MPMC_EINVAL (N == 0, eta outside (0, pi/4], M < 4, w + d >= 4,
+ * non-square N with a lattice start, bad step or trial count),
+ * MPMC_ENOMEM, MPMC_EDEVICE. */
+int mpmc_init_box(mpmc_box *out, uint32_t N, double eta, uint64_t seed, const mpmc_params *p);
+
+/* Releases all device memory of the box.  b == NULL is allowed. */
+int mpmc_free_box(mpmc_box b);
+
+/* Replaces the configuration: disk t (tag t) at absolute position
+ * (X[t], Y[t]) in q units, 0 <= X, Y < M W (host arrays of N).  Resets the
+ * accumulated shift.  MPMC_EOVERFLOW if a cell would exceed its capacity. */
+int mpmc_set_positions(mpmc_box b, const int64_t *X, const int64_t *Y);
+
+/* Changes the trial step (1..255); for tuning during equilibration only. */
+int mpmc_set_step(mpmc_box b, uint32_t step_m);
+
+/* Runs k sweeps (Sec. II.B).  Sweep s: (1) shift the cell grid by a random
+ * multiple of q in [0, w)^2 and re-bin; (2) visit the four colour subsets in
+ * a random order; in each, every non-empty cell makes n_trial trials.  The
+ * Philox4x32-10 counter layout (seed; sweep, cell, trial, stream) makes the
+ * result independent of launch shape.  Asynchronous unless trials or accepts
+ * is non-NULL: then it synchronises and returns the counts of this call. */
+int mpmc_sweep(mpmc_box b, uint64_t k, uint64_t *trials, uint64_t *accepts);
+
+/* Adds the current configuration to the device contact histogram: unordered
+ * pairs with 4 <= fp32 r^2 < fp32((2 + K dr)^2), bin k holding
+ * fp32((2 + k dr)^2) <= r^2 < fp32((2 + (k+1) dr)^2) (Eq. (2) counting). */
+int mpmc_accumulate_contacts(mpmc_box b);
+int mpmc_reset_contacts(mpmc_box b);
+/* Copies the K unordered counts and the number of configurations. */
+int mpmc_get_contacts(mpmc_box b, int64_t *counts, uint64_t *n_conf);
+
+/* Pressure from the accumulated histogram (Sec. II.C.1): g_k from Eq. (2)
+ * with p = N(N-1)/2 pairs per configuration and r_k the bin centre; an
+ * unweighted least-squares polynomial (fit_order) in r - 2 gives g(2+);
+ * Z = 1 + 2 eta (N-1)/N g(2+) (Eq. (4) at finite N); P* = 4 eta Z / pi
+ * (Eq. (1)).  *se is the standard error of P* over completed blocks of
+ * hist_block configurations (NaN if fewer than 2).  Any output may be NULL.
+ * MPMC_ESTATE if nothing was accumulated. */
+int mpmc_measure_pressure(mpmc_box b, double *p_star, double *g_contact, double *z, double *se);
+
+/* Diagnostic: ordered pair counts (i, j != i) of the current configuration
+ * for the disks i with sel[tag] != 0 (host array of N), into counts[K]. */
+int mpmc_contact_hist_subset(mpmc_box b, const uint8_t *sel, int64_t *counts);
+
+/* Orientational order, Eq. (8): psi_j = (1/6) sum over the six nearest
+ * neighbours (fp32 minimum-image r^2, ties to the lower tag) of
+ * exp(6 i phi_jk), phi from the +x axis, evaluated as (z^2)^3 / |z|^6.
+ * re/im: psi_j by tag (N floats each); field_re/field_im: per cell of the
+ * current grid (M*M floats, cell i + M j), the mean psi_j over its 3 x 3
+ * block; Psi: the global mean (Sec. III).  Array outputs are device pointers
+ * when on_device != 0, else host; any output may be NULL.  MPMC_EINVAL if
+ * N < 7 or the neighbourhood search would span the box. */
+int mpmc_psi6_field(mpmc_box b, float *re, float *im, float *field_re, float *field_im,
+                    double *Psi_re, double *Psi_im, int on_device);
+
+/* Absolute positions by tag: (i w + u + S) mod L_eff in sigma (double) or
+ * in q units (int64); either pair may be NULL. */
+int mpmc_get_positions(mpmc_box b, double *x, double *y, int64_t *X, int64_t *Y);
+
+/* Cell lists of the current grid in their canonical slot order: cnt[M*M],
+ * tag/x/y[M*M*cap] (slot s of cell c at c*cap + s, unused slots 0).  The
+ * order after each re-bin: disks of old cell (I, J) that stay, then those
+ * of (I+1, J) wrapping in x, of (I, J+1) wrapping in y, of (I+1, J+1)
+ * wrapping in both, each in old slot order. */
+int mpmc_get_cells(mpmc_box b, uint8_t *cnt, uint32_t *tag, float *x, float *y);
+
+int mpmc_get_info(mpmc_box b, mpmc_info *info);
+
+/* Checks the state on the device: *n_overlaps = unordered pairs with
+ * fp32 r^2 < 4 (3 x 3 cell stencil, exhaustive since w >= 2 sigma);
+ * *n_bad = offsets outside [0, w) plus count, tag and capacity violations. */
+int mpmc_validate(mpmc_box b, uint64_t *n_overlaps, uint64_t *n_bad);
+
+/* Checkpoint: writes the cell lists, shift, sweep counter, counters, step,
+ * seed and the contact histogram to `path`; mpmc_load creates a box from
+ * it (p supplies stream, allocator and schedule; NULL = defaults).
+ * Continuing a loaded box reproduces the uninterrupted run bit for bit. */
+int mpmc_save(mpmc_box b, const char *path);
+int mpmc_load(mpmc_box *out, const char *path, const mpmc_params *p);
+
+/* Time-series analysis of Sec. III on host arrays.  mpmc_acf: C(dt) of
+ * Eq. (9) for dt = 0..maxlag from a complex series of length n, the real
+ * part of the mean over all time origins of Psi(t) Psi*(t+dt) over the mean
+ * of |Psi|^2.  mpmc_tau: tau of the exponential tail, from least squares of
+ * ln C over the first run of lags with lo <= C <= hi (MPMC_ESTATE if fewer
+ * than 3 such lags), and the integrated time 1/2 + sum C up to the first
+ * lag >= 6 tau_int (either output may be NULL). */
+int mpmc_acf(const double *re, const double *im, uint32_t n, uint32_t maxlag, double *C);
+int mpmc_tau(const double *C, uint32_t maxlag, double lo, double hi, double *tau,
+             double *tau_int);
+
+/* Sweep schedule of an existing box: MPMC_SCHED_SIMPLE, MPMC_SCHED_FUSED
+ * with the given tile side and threads per workgroup (0 = default), or
+ * MPMC_SCHED_AUTO (autotune: time every fused shape that fits on this machine's
+ * state, keep the fastest; cached per device, M and n_trial).  The state
+ * and the trajectory are unaffected.  MPMC_EINVAL if the shape does not fit
+ * (fused tiles need cells of at most 4 disks and an even tile <= M). */
+int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t threads);
+
+/* Long runs replay a captured HIP graph of this many sweeps (even, default
+ * 128 fused / 32 simple); 0 launches every sweep directly. */
+int mpmc_set_graphs(mpmc_box b, uint32_t sweeps_per_graph);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *mpmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

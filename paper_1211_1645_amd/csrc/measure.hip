@@ -1,0 +1,255 @@
+// measure.hip — observables on the device: the contact pair histogram behind
+// the pressure (Sec. II.C.1, Eq. (2)), the local orientational order psi_j
+// and its coarse field (Eq. (8), Secs. III and IV.B), the state validator
+// and the absolute positions.  One thread per cell or per cell slot; the
+// cell grid bounds every neighbour search (w >= 2 sigma).
+#include "mpmc_kernels.hpp"
+
+namespace mpmc {
+
+__device__ __forceinline__ uint32_t wrapc(int v, uint32_t M) {
+    int r = v % (int)M;
+    return (uint32_t)(r < 0 ? r + (int)M : r);
+}
+
+// ---------------------------------------------------------------------------
+// Contact histogram: for every disk i (optionally restricted by sel[tag]) and
+// every disk j != i in the (2h+1)^2 cell stencil, bin fp32 r^2 against the
+// squared edges.  Pairs are counted ordered; an unordered count is half.
+// With h = 2 and M = 4 a cell is visited at offsets -2 and +2, i.e. as two
+// different periodic images, of which at most one lies below r_max < L/2.
+__global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float *__restrict__ E,
+                                                      uint32_t K, int h,
+                                                      unsigned long long *hist,
+                                                      const uint8_t *sel) {
+    extern __shared__ uint32_t bins[];
+    for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
+    __syncthreads();
+    const uint32_t M = m.M;
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell < M * M) {
+        const uint32_t ci = cell % M, cj = cell / M;
+        const uint32_t n = m.cnt[cell];
+        const float e0 = E[0], eK = E[K];
+        for (uint32_t s = 0; s < n; ++s) {
+            if (sel && !sel[m.tag[cell * m.CS + s]]) continue;
+            const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
+            for (int dj = -h; dj <= h; ++dj)
+                for (int di = -h; di <= h; ++di) {
+                    const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+                    const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                    const uint32_t mm = m.cnt[nb];
+                    for (uint32_t t = 0; t < mm; ++t) {
+                        if (di == 0 && dj == 0 && t == s) continue;
+                        const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
+                        const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
+                        const float r2 = r2_f32(dx, dy);
+                        if (!(r2 >= e0) || !(r2 < eK)) continue;
+                        // start from the square-root estimate, then settle
+                        // on the exact fp32 edges
+                        int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
+                        k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
+                        while (k > 0 && r2 < E[k]) --k;
+                        while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
+                        atomicAdd(&bins[k], 1u);
+                    }
+                }
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < K; k += blockDim.x)
+        if (bins[k]) atomicAdd(&hist[k], (unsigned long long)bins[k]);
+}
+
+void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
+                         unsigned long long *hist, const uint8_t *sel, hipStream_t st) {
+    const uint32_t nc = m.M * m.M;
+    k_contact_hist<<<(nc + 255) / 256, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, hist, sel);
+}
+
+// ---------------------------------------------------------------------------
+// psi_j: the six nearest other disks by (fp32 r^2, tag) within the
+// (2h+1)^2 stencil.  The search is exact when the sixth distance is below
+// h w (every disk closer than h w lies in the stencil); otherwise the disk
+// sets *fail and the host repeats with a larger h.
+struct Nb6 {
+    float r2[6];
+    uint32_t tag[6];
+    float dx[6], dy[6];
+};
+
+__device__ __forceinline__ bool nb_less(float ra, uint32_t ta, float rb, uint32_t tb) {
+    return ra < rb || (ra == rb && ta < tb);
+}
+
+__global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, float *im,
+                                              uint32_t *fail) {
+    const uint32_t M = m.M;
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t cell = gid / m.CS, s = gid % m.CS;
+    double pr = 0.0, pi = 0.0;
+    if (cell < M * M && s < m.cnt[cell]) {
+        const uint32_t ci = cell % M, cj = cell / M;
+        const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
+        const uint32_t ti = m.tag[cell * m.CS + s];
+        Nb6 b;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
+        for (int dj = -h; dj <= h; ++dj)
+            for (int di = -h; di <= h; ++di) {
+                const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+                const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                const uint32_t mm = m.cnt[nb];
+                for (uint32_t t = 0; t < mm; ++t) {
+                    if (di == 0 && dj == 0 && t == s) continue;
+                    const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
+                    const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
+                    const float r2 = r2_f32(dx, dy);
+                    const uint32_t tg = m.tag[nb * m.CS + t];
+                    if (!nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
+                    b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
+#pragma unroll
+                    for (int e = 5; e > 0; --e) {
+                        if (nb_less(b.r2[e], b.tag[e], b.r2[e - 1], b.tag[e - 1])) {
+                            float fr = b.r2[e]; b.r2[e] = b.r2[e - 1]; b.r2[e - 1] = fr;
+                            uint32_t ft = b.tag[e]; b.tag[e] = b.tag[e - 1]; b.tag[e - 1] = ft;
+                            float fx = b.dx[e]; b.dx[e] = b.dx[e - 1]; b.dx[e - 1] = fx;
+                            float fy = b.dy[e]; b.dy[e] = b.dy[e - 1]; b.dy[e - 1] = fy;
+                        }
+                    }
+                }
+            }
+        const double reach = (double)h * (double)m.w;
+        if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
+        float sr = 0.0f, si = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const float dx = b.dx[e], dy = b.dy[e];
+            const float ar = dx * dx - dy * dy, ai = 2.0f * dx * dy;     // z^2
+            const float br = ar * ar - ai * ai, bi = 2.0f * ar * ai;     // z^4
+            const float cr = br * ar - bi * ai, cim = br * ai + bi * ar; // z^6
+            const float r6 = b.r2[e] * b.r2[e] * b.r2[e];
+            sr += cr / r6;
+            si += cim / r6;
+        }
+        sr *= (1.0f / 6.0f);
+        si *= (1.0f / 6.0f);
+        re[ti] = sr;
+        im[ti] = si;
+        pr = sr;
+        pi = si;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        pr += __shfl_xor(pr, off, 64);
+        pi += __shfl_xor(pi, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+        atomicAdd(&m.dev->psi_re, pr);
+        atomicAdd(&m.dev->psi_im, pi);
+    }
+}
+
+void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
+                 hipStream_t st) {
+    const uint32_t n = m.M * m.M * m.CS;
+    k_psi6<<<(n + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail);
+}
+
+// Coarse field: per cell, the mean psi_j over the disks of its 3 x 3 block.
+__global__ void __launch_bounds__(256) k_psi6_field(MeasureView m, const float *re,
+                                                    const float *im, float *fre, float *fim) {
+    const uint32_t M = m.M;
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= M * M) return;
+    const uint32_t ci = cell % M, cj = cell / M;
+    float sr = 0.0f, si = 0.0f;
+    uint32_t n = 0;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+            const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+            for (uint32_t t = 0; t < m.cnt[nb]; ++t) {
+                const uint32_t tg = m.tag[nb * m.CS + t];
+                sr += re[tg];
+                si += im[tg];
+                ++n;
+            }
+        }
+    fre[cell] = n ? sr / (float)n : 0.0f;
+    fim[cell] = n ? si / (float)n : 0.0f;
+}
+
+void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
+                       float *fim, hipStream_t st) {
+    const uint32_t nc = m.M * m.M;
+    k_psi6_field<<<(nc + 255) / 256, 256, 0, st>>>(m, re, im, fre, fim);
+}
+
+// ---------------------------------------------------------------------------
+// Validator: offsets in [0, w), counts within capacity, every tag exactly
+// once, and no pair closer than 2 sigma in the 3 x 3 stencil (exhaustive for
+// w >= 2 sigma).  Overlaps are counted ordered.
+__global__ void __launch_bounds__(256) k_validate(MeasureView m, uint32_t *tag_seen) {
+    const uint32_t M = m.M;
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bad = 0, ov = 0;
+    if (cell < M * M) {
+        const uint32_t ci = cell % M, cj = cell / M;
+        uint32_t n = m.cnt[cell];
+        if (n > m.cap) { ++bad; n = m.cap; }
+        for (uint32_t s = 0; s < n; ++s) {
+            const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
+            const uint32_t tg = m.tag[cell * m.CS + s];
+            if (!(xi >= 0.0f && xi < m.w && yi >= 0.0f && yi < m.w)) ++bad;
+            if (tg < m.N) atomicAdd(&tag_seen[tg], 1u); else ++bad;
+            for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                    const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+                    const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                    uint32_t mm = m.cnt[nb];
+                    mm = mm > m.cap ? m.cap : mm;
+                    for (uint32_t t = 0; t < mm; ++t) {
+                        if (di == 0 && dj == 0 && t == s) continue;
+                        const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
+                        const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
+                        if (overlap_f32(dx, dy)) ++ov;
+                    }
+                }
+        }
+    }
+    if (bad) atomicAdd(&m.dev->bad, bad);
+    if (ov) atomicAdd(&m.dev->overlaps, ov);
+}
+
+__global__ void k_tags_once(const uint32_t *tag_seen, uint32_t N, DevScalars *dev) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N && tag_seen[t] != 1u) atomicAdd(&dev->bad, 1ull);
+}
+
+void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st) {
+    const uint32_t nc = m.M * m.M;
+    k_validate<<<(nc + 255) / 256, 256, 0, st>>>(m, tag_seen);
+    k_tags_once<<<(m.N + 255) / 256, 256, 0, st>>>(tag_seen, m.N, m.dev);
+}
+
+// ---------------------------------------------------------------------------
+// Absolute q position of every disk, by tag: (i W + U + S) mod (M W).
+__global__ void __launch_bounds__(256) k_positions(MeasureView m, long long *X, long long *Y) {
+    const uint32_t M = m.M;
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t cell = gid / m.CS, s = gid % m.CS;
+    if (cell >= M * M || s >= m.cnt[cell]) return;
+    const long long U = (long long)(m.x[cell * m.CS + s] * 4194304.0f);
+    const long long V = (long long)(m.y[cell * m.CS + s] * 4194304.0f);
+    const uint32_t tg = m.tag[cell * m.CS + s];
+    if (tg >= m.N) return;
+    X[tg] = ((long long)(cell % M) * m.W + U + m.Sx) % m.Lq;
+    Y[tg] = ((long long)(cell / M) * m.W + V + m.Sy) % m.Lq;
+}
+
+void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st) {
+    const uint32_t n = m.M * m.M * m.CS;
+    k_positions<<<(n + 255) / 256, 256, 0, st>>>(m, X, Y);
+}
+
+}  // namespace mpmc

@@ -1,0 +1,89 @@
+// mpmc_host.hpp — host-side state of one box (behind the opaque mpmc_box).
+#pragma once
+#include <stdarg.h>
+
+#include <vector>
+
+#include "../../include/mpmc.h"
+#include "mpmc_kernels.hpp"
+
+namespace mpmc {
+
+// Records a message for mpmc_last_error() and returns code.
+int fail(int code, const char *fmt, ...);
+
+struct Geometry {
+    double L;      // nominal side sqrt(N pi / eta)
+    uint32_t M;    // cells per side
+    int64_t W;     // cell width in q units
+    float w;       // cell width (exact fp32)
+    int64_t Lq;    // simulated side M W in q units
+    uint32_t cap;  // disks a cell can hold
+    uint32_t CS;   // slot stride of the cell arrays (4 or 8)
+};
+
+int compute_geometry(Geometry *g, uint32_t N, double eta, double cell_min, uint32_t step_m);
+int build_cells(const Geometry &g, uint32_t N, const int64_t *X, const int64_t *Y,
+                std::vector<uint8_t> &hc, std::vector<uint32_t> &ht, std::vector<float> &hx,
+                std::vector<float> &hy);
+
+struct Box {
+    uint32_t N = 0;
+    double eta = 0;
+    uint64_t seed = 0;
+    mpmc_params p{};
+    Geometry g{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    // double-buffered SoA cell lists; `cur` holds the current state
+    uint8_t *cnt[2] = {nullptr, nullptr};
+    float *x[2] = {nullptr, nullptr}, *y[2] = {nullptr, nullptr};
+    uint32_t *tag[2] = {nullptr, nullptr};
+    int cur = 0;
+    bool placed = true;
+    DevScalars *dev = nullptr;
+    DevScalars host{};
+    unsigned long long *hist = nullptr;  // ordered pair counts
+    float *edges = nullptr;
+    uint32_t *scratch_u32 = nullptr;
+    void *pos_scratch[2] = {nullptr, nullptr};
+    float *psi_buf = nullptr;  // re[N], im[N], field re/im[M*M]
+    uint64_t n_conf = 0;
+    // blocks for the pressure standard error
+    std::vector<unsigned long long> block_snapshot;
+    uint64_t block_conf0 = 0;
+    std::vector<double> block_P;
+    // schedule
+    uint32_t sched = MPMC_SCHED_SIMPLE;
+    FusedShape shape{0, 0};
+    bool use_graphs = true;
+    uint32_t graph_sweeps = 64;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    uint64_t host_sweeps = 0;
+    std::vector<void *> allocations;
+
+    int alloc_dev(void **ptr, size_t bytes);
+    void release();
+    BoxView view(int from) const;
+    MeasureView mview() const;
+    int sync();
+    int read_scalars();
+    int upload(const std::vector<uint8_t> &hc, const std::vector<uint32_t> &ht,
+               const std::vector<float> &hx, const std::vector<float> &hy, const DevScalars &s);
+    int launch_one(int from, uint32_t offset, hipStream_t st);
+    int build_graph();
+    uint64_t key() const;
+    int run_sweeps(uint64_t k);
+    int choose_schedule();
+    void *scratch_pos(int which);
+};
+
+int create_box(Box **out, uint32_t N, double eta, uint64_t seed, const mpmc_params *p);
+
+// Unweighted least-squares polynomial of `order` through (t_k, y_k), by
+// Householder QR; returns 0 and the coefficients, or -1 if singular.
+int lsq_poly(const std::vector<double> &t, const std::vector<double> &yv, uint32_t order,
+             double *coef);
+
+}  // namespace mpmc

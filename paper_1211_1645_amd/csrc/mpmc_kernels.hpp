@@ -1,0 +1,63 @@
+// mpmc_kernels.hpp — device helpers and launch wrappers of the MPMC library.
+#pragma once
+#include "mpmc_common.hpp"
+
+namespace mpmc {
+
+// Workgroup sum of the per-lane trial and acceptance counts: a wave
+// reduction, one LDS atomic per wave, then one 64-bit global atomic per
+// workgroup into slot (blockIdx mod 64).  Every thread of the workgroup must
+// call it (it contains barriers).
+__device__ __forceinline__ void count_trials(DevScalars *dev, uint32_t t, uint32_t a) {
+    __shared__ uint32_t red[2];
+    if (threadIdx.x == 0) { red[0] = 0; red[1] = 0; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        t += __shfl_xor(t, off, 64);
+        a += __shfl_xor(a, off, 64);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0 && t != 0) {
+        atomicAdd(&red[0], t);
+        atomicAdd(&red[1], a);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && red[0] != 0) {
+        const uint32_t s = blockIdx.x % kCountSlots;
+        atomicAdd(&dev->slot_trials[s], (unsigned long long)red[0]);
+        atomicAdd(&dev->slot_accepts[s], (unsigned long long)red[1]);
+    }
+}
+
+// sweep_simple.hip
+void launch_simple_sweep(const BoxView &v, hipStream_t st);
+void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,
+                    long long Lq, uint32_t count, hipStream_t st);
+
+// sweep_fused.hip
+struct FusedShape { uint32_t tile, threads; };
+bool fused_supported(const BoxView &v, const FusedShape &s);
+const FusedShape *fused_shapes(uint32_t *count);
+void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st);
+
+// measure.hip
+struct MeasureView {
+    const uint8_t *cnt;
+    const float *x, *y;
+    const uint32_t *tag;
+    DevScalars *dev;
+    uint32_t M, W, cap, CS, N;
+    float w;
+    long long Sx, Sy, Lq;
+};
+// h: stencil half-width in cells (1 when w covers the histogram range)
+void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
+                         unsigned long long *hist, const uint8_t *sel, hipStream_t st);
+void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
+                 hipStream_t st);
+void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
+                       float *fim, hipStream_t st);
+void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);
+void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st);
+
+}  // namespace mpmc

@@ -1,0 +1,326 @@
+"""Python binding of the MI355X MPMC hard-disk library (libmpmc.so).
+
+Argument marshalling only: every step of the sampler and of the observables
+runs inside the HIP library.  PyTorch supplies the stream (and optionally the
+caching allocator) for device work.  There is no fallback: if the library is
+not built, every call raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpmc.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EOVERFLOW, EIO = 0, -1, -2, -3, -4, -5, -6
+LATTICE = {"square": 0, "triangular": 1, "none": 2}
+SCHEDULE = {"auto": 0, "simple": 1, "fused": 2}
+Q = 2.0 ** -22
+
+_alloc_t = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_free_t = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Params(C.Structure):
+    _fields_ = [("step_m", C.c_uint32), ("n_trial", C.c_uint32), ("lattice", C.c_int32),
+                ("cell_min", C.c_double), ("hist_dr", C.c_double), ("hist_bins", C.c_uint32),
+                ("fit_order", C.c_uint32), ("hist_block", C.c_uint32), ("schedule", C.c_uint32),
+                ("tile", C.c_uint32), ("stream", C.c_void_p), ("alloc", _alloc_t),
+                ("free", _free_t), ("alloc_ctx", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_uint32), ("M", C.c_uint32), ("cap", C.c_uint32), ("n_trial", C.c_uint32),
+                ("step_m", C.c_uint32), ("tile", C.c_uint32), ("schedule", C.c_uint32),
+                ("hist_bins", C.c_uint32), ("W", C.c_int64), ("L", C.c_double),
+                ("L_eff", C.c_double), ("w", C.c_double), ("eta", C.c_double),
+                ("eta_eff", C.c_double), ("hist_dr", C.c_double), ("sweep", C.c_uint64),
+                ("Sx", C.c_int64), ("Sy", C.c_int64), ("trials", C.c_uint64),
+                ("accepts", C.c_uint64), ("n_conf", C.c_uint64)]
+
+
+class MPMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("MPMC error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes); every function declared in include/mpmc.h
+_P = C.c_void_p
+_SIGS = {
+    "mpmc_default_params": [C.POINTER(Params)],
+    "mpmc_init_box": [C.POINTER(C.c_void_p), C.c_uint32, C.c_double, C.c_uint64, C.POINTER(Params)],
+    "mpmc_free_box": [_P],
+    "mpmc_set_positions": [_P, _P, _P],
+    "mpmc_set_step": [_P, C.c_uint32],
+    "mpmc_sweep": [_P, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+    "mpmc_accumulate_contacts": [_P],
+    "mpmc_reset_contacts": [_P],
+    "mpmc_get_contacts": [_P, _P, C.POINTER(C.c_uint64)],
+    "mpmc_measure_pressure": [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "mpmc_contact_hist_subset": [_P, _P, _P],
+    "mpmc_psi6_field": [_P, _P, _P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int],
+    "mpmc_get_positions": [_P, _P, _P, _P, _P],
+    "mpmc_get_cells": [_P, _P, _P, _P, _P],
+    "mpmc_get_info": [_P, C.POINTER(Info)],
+    "mpmc_validate": [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+    "mpmc_save": [_P, C.c_char_p],
+    "mpmc_load": [C.POINTER(C.c_void_p), C.c_char_p, C.POINTER(Params)],
+    "mpmc_acf": [_P, _P, C.c_uint32, C.c_uint32, _P],
+    "mpmc_tau": [_P, C.c_uint32, C.c_double, C.c_double, C.POINTER(C.c_double),
+                 C.POINTER(C.c_double)],
+    "mpmc_set_schedule": [_P, C.c_uint32, C.c_uint32, C.c_uint32],
+    "mpmc_set_graphs": [_P, C.c_uint32],
+}
+
+
+def load():
+    """Loads libmpmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmpmc.so is not built (run __graft_entry__.build() or "
+                           "python paper_1211_1645_amd/build.py); there is no fallback")
+    lib = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.mpmc_last_error.restype = C.c_char_p
+    lib.mpmc_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise MPMCError(rc, _lib.mpmc_last_error().decode())
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+class _TorchAllocator:
+    """Device memory from torch's caching allocator, through the ABI hook."""
+
+    def __init__(self, stream):
+        import torch
+        self.torch = torch
+        self.stream = stream
+        self.a = _alloc_t(self._alloc)
+        self.f = _free_t(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), stream=self.stream)
+        except Exception:
+            return None
+
+    def _free(self, ptr, ctx):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Box:
+    """N hard disks in a periodic square box, sampled by MPMC on the GPU."""
+
+    def __init__(self, N, eta, seed=0, step_m=26, n_trial=1, lattice="triangular", cell_min=2.0,
+                 hist_dr=1e-3, hist_bins=100, fit_order=4, hist_block=0, schedule="auto",
+                 tile=0, stream=None, torch_allocator=False, _handle=None):
+        lib = load()
+        self._alloc = None
+        if _handle is None:
+            p = self._params(step_m, n_trial, lattice, cell_min, hist_dr, hist_bins, fit_order,
+                             hist_block, schedule, tile, stream, torch_allocator)
+            h = C.c_void_p()
+            _check(lib.mpmc_init_box(C.byref(h), N, eta, seed, C.byref(p)))
+            _handle = h
+        self.h = _handle
+        i = self.info()
+        self.N, self.M, self.cap = i["N"], i["M"], i["cap"]
+
+    def _params(self, step_m=26, n_trial=1, lattice="triangular", cell_min=2.0, hist_dr=1e-3,
+                hist_bins=100, fit_order=4, hist_block=0, schedule="auto", tile=0, stream=None,
+                torch_allocator=False):
+        p = Params()
+        _check(load().mpmc_default_params(C.byref(p)))
+        p.step_m, p.n_trial = step_m, n_trial
+        p.lattice = LATTICE[lattice] if isinstance(lattice, str) else lattice
+        p.cell_min, p.hist_dr, p.hist_bins, p.fit_order = cell_min, hist_dr, hist_bins, fit_order
+        p.hist_block = hist_block
+        p.schedule = SCHEDULE[schedule] if isinstance(schedule, str) else schedule
+        p.tile = tile
+        st = stream if stream is not None else _current_stream()
+        p.stream = st
+        if torch_allocator:
+            self._alloc = _TorchAllocator(st)
+            p.alloc, p.free = self._alloc.a, self._alloc.f
+        return p
+
+    @classmethod
+    def load(cls, path, stream=None, schedule="auto"):
+        lib = load()
+        b = cls.__new__(cls)
+        b._alloc = None
+        p = b._params(schedule=schedule, stream=stream)
+        h = C.c_void_p()
+        _check(lib.mpmc_load(C.byref(h), path.encode(), C.byref(p)))
+        cls.__init__(b, 0, 0.0, _handle=h)
+        return b
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.mpmc_free_box(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- sampling ---------------------------------------------------------
+    def sweep(self, k=1, counts=False):
+        if counts:
+            t, a = C.c_uint64(), C.c_uint64()
+            _check(_lib.mpmc_sweep(self.h, k, C.byref(t), C.byref(a)))
+            return t.value, a.value
+        _check(_lib.mpmc_sweep(self.h, k, None, None))
+        return None
+
+    def set_step(self, m):
+        _check(_lib.mpmc_set_step(self.h, m))
+
+    def set_positions_q(self, X, Y):
+        X = np.ascontiguousarray(X, np.int64)
+        Y = np.ascontiguousarray(Y, np.int64)
+        _check(_lib.mpmc_set_positions(self.h, _ptr(X), _ptr(Y)))
+
+    def set_schedule(self, schedule, tile=0, threads=0):
+        s = SCHEDULE[schedule] if isinstance(schedule, str) else schedule
+        _check(_lib.mpmc_set_schedule(self.h, s, tile, threads))
+
+    def set_graphs(self, sweeps_per_graph):
+        _check(_lib.mpmc_set_graphs(self.h, sweeps_per_graph))
+
+    # ---- observables --------------------------------------------------------
+    def accumulate_contacts(self):
+        _check(_lib.mpmc_accumulate_contacts(self.h))
+
+    def reset_contacts(self):
+        _check(_lib.mpmc_reset_contacts(self.h))
+
+    def contacts(self):
+        K = self.info()["hist_bins"]
+        c = np.zeros(K, np.int64)
+        n = C.c_uint64()
+        _check(_lib.mpmc_get_contacts(self.h, _ptr(c), C.byref(n)))
+        return c, n.value
+
+    def measure_pressure(self):
+        P, g, Z, se = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.mpmc_measure_pressure(self.h, C.byref(P), C.byref(g), C.byref(Z), C.byref(se)))
+        return dict(P_star=P.value, g_contact=g.value, Z=Z.value, se=se.value)
+
+    def contact_hist_subset(self, sel):
+        K = self.info()["hist_bins"]
+        sel = np.ascontiguousarray(sel, np.uint8)
+        c = np.zeros(K, np.int64)
+        _check(_lib.mpmc_contact_hist_subset(self.h, _ptr(sel), _ptr(c)))
+        return c
+
+    def psi6_field(self, device=False):
+        """Returns (psi_j by tag, field per cell, Psi_6)."""
+        r, i = C.c_double(), C.c_double()
+        if device:
+            import torch
+            psi = torch.empty(self.N, 2, dtype=torch.float32, device="cuda")
+            re = torch.empty(self.N, dtype=torch.float32, device="cuda")
+            im = torch.empty(self.N, dtype=torch.float32, device="cuda")
+            fre = torch.empty(self.M * self.M, dtype=torch.float32, device="cuda")
+            fim = torch.empty(self.M * self.M, dtype=torch.float32, device="cuda")
+            _check(_lib.mpmc_psi6_field(self.h, C.c_void_p(re.data_ptr()), C.c_void_p(im.data_ptr()),
+                                        C.c_void_p(fre.data_ptr()), C.c_void_p(fim.data_ptr()),
+                                        C.byref(r), C.byref(i), 1))
+            del psi
+            return torch.complex(re, im), torch.complex(fre, fim), complex(r.value, i.value)
+        re = np.zeros(self.N, np.float32)
+        im = np.zeros(self.N, np.float32)
+        fre = np.zeros(self.M * self.M, np.float32)
+        fim = np.zeros(self.M * self.M, np.float32)
+        _check(_lib.mpmc_psi6_field(self.h, _ptr(re), _ptr(im), _ptr(fre), _ptr(fim), C.byref(r),
+                                    C.byref(i), 0))
+        return re + 1j * im.astype(np.complex64), fre + 1j * fim.astype(np.complex64), \
+            complex(r.value, i.value)
+
+    def psi6(self):
+        """Global Psi_6 only (Sec. III)."""
+        r, i = C.c_double(), C.c_double()
+        _check(_lib.mpmc_psi6_field(self.h, None, None, None, None, C.byref(r), C.byref(i), 0))
+        return complex(r.value, i.value)
+
+    # ---- state ------------------------------------------------------------
+    def info(self):
+        i = Info()
+        _check(_lib.mpmc_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def positions_q(self):
+        X = np.zeros(self.N, np.int64)
+        Y = np.zeros(self.N, np.int64)
+        _check(_lib.mpmc_get_positions(self.h, None, None, _ptr(X), _ptr(Y)))
+        return X, Y
+
+    def positions(self):
+        x = np.zeros(self.N, np.float64)
+        y = np.zeros(self.N, np.float64)
+        _check(_lib.mpmc_get_positions(self.h, _ptr(x), _ptr(y), None, None))
+        return x, y
+
+    def cells(self):
+        nc = self.M * self.M
+        cnt = np.zeros(nc, np.uint8)
+        tag = np.zeros(nc * self.cap, np.uint32)
+        x = np.zeros(nc * self.cap, np.float32)
+        y = np.zeros(nc * self.cap, np.float32)
+        _check(_lib.mpmc_get_cells(self.h, _ptr(cnt), _ptr(tag), _ptr(x), _ptr(y)))
+        return cnt, tag.reshape(nc, self.cap), x.reshape(nc, self.cap), y.reshape(nc, self.cap)
+
+    def validate(self):
+        o, b = C.c_uint64(), C.c_uint64()
+        _check(_lib.mpmc_validate(self.h, C.byref(o), C.byref(b)))
+        return o.value, b.value
+
+    def save(self, path):
+        _check(_lib.mpmc_save(self.h, path.encode()))
+
+
+def acf(series, maxlag):
+    """C(dt) of Eq. (9) computed by the library's host analysis."""
+    load()
+    s = np.asarray(series, np.complex128)
+    re, im = np.ascontiguousarray(s.real), np.ascontiguousarray(s.imag)
+    out = np.zeros(maxlag + 1, np.float64)
+    _check(_lib.mpmc_acf(_ptr(re), _ptr(im), len(s), maxlag, _ptr(out)))
+    return out
+
+
+def tau(Cv, lo=0.05, hi=0.5):
+    """(tau from the exponential tail, integrated tau)."""
+    load()
+    Cv = np.ascontiguousarray(Cv, np.float64)
+    t, ti = C.c_double(), C.c_double()
+    _check(_lib.mpmc_tau(_ptr(Cv), len(Cv) - 1, lo, hi, C.byref(t), C.byref(ti)))
+    return t.value, ti.value

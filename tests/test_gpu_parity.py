@@ -1,0 +1,226 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+The plain sampler is compared bit for bit: cell lists (counts, tags, fp32
+offsets in slot order), absolute positions, shifts and trial counters after
+k sweeps.  Integer observables (contact counts) must be identical; psi_6 is
+compared within 1e-5 per disk (fp32 on the GPU, fp64 in the oracle, same
+neighbour sets).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from oracle.orc import OracleBox
+
+pytestmark = pytest.mark.gpu
+
+CONFIG1 = dict(N=256, eta=0.60, seed=0, lattice=0, step_m=26)
+CONFIG2 = dict(N=65536, eta=0.716, seed=0, lattice=1, step_m=20)
+
+
+def gpu_box(mp, N, eta, seed, lattice, step_m, n_trial=1, **kw):
+    return mp.Box(N, eta, seed=seed, step_m=step_m, n_trial=n_trial,
+                  lattice={0: "square", 1: "triangular", 2: "none"}[lattice], **kw)
+
+
+def assert_same_state(g, o):
+    gi, oi = g.info(), o.info()
+    for k in ("sweep", "Sx", "Sy", "trials", "accepts", "M", "W"):
+        assert gi[k] == oi[k], (k, gi[k], oi[k])
+    gc, ocl = g.cells(), o.cells()
+    names = ("cnt", "tag", "x", "y")
+    for name, a, b in zip(names, gc, ocl):
+        if a.dtype == np.float32:
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), name
+        else:
+            assert np.array_equal(a, b), name
+    gX, gY = g.positions_q()
+    oX, oY = o.positions_q()
+    assert np.array_equal(gX, oX) and np.array_equal(gY, oY)
+
+
+@pytest.mark.parametrize("schedule,tile,threads", [("simple", 0, 0), ("fused", 8, 64), ("fused", 8, 128)])
+def test_config1_trajectory_bit_exact(gpu_lib, schedule, tile, threads):
+    g = gpu_box(gpu_lib, **CONFIG1, schedule="simple")
+    g.set_schedule(schedule, tile, threads)
+    o = OracleBox(**CONFIG1)
+    assert_same_state(g, o)
+    done = 0
+    for k in (1, 10, 100, 1000):
+        g.sweep(k - done)
+        o.sweep(k - done)
+        done = k
+        assert_same_state(g, o)
+    assert g.validate() == (0, 0)
+
+
+@pytest.mark.parametrize("n_trial", [2, 4])
+def test_shuffled_trials_bit_exact(gpu_lib, n_trial):
+    for schedule, tile in (("simple", 0), ("fused", 8)):
+        g = gpu_box(gpu_lib, **CONFIG1, n_trial=n_trial, schedule=schedule, tile=tile)
+        o = OracleBox(**CONFIG1, n_trial=n_trial)
+        g.sweep(57)
+        o.sweep(57)
+        assert_same_state(g, o)
+
+
+def test_config2_trajectory_bit_exact(gpu_lib):
+    g = gpu_box(gpu_lib, **CONFIG2)  # autotuned fused schedule
+    assert g.info()["schedule"] == 2
+    o = OracleBox(**CONFIG2)
+    done = 0
+    for k in (1, 10, 60):
+        g.sweep(k - done)
+        o.sweep(k - done)
+        done = k
+        assert_same_state(g, o)
+    assert g.validate() == (0, 0)
+
+
+def test_schedule_invariance_all_shapes(gpu_lib):
+    """Every schedule (simple, each fused tile/threads shape, graphs on or
+    off) gives the same trajectory."""
+    ref = gpu_box(gpu_lib, **CONFIG2, schedule="simple")
+    ref.sweep(20)
+    rc = ref.cells()
+    shapes = [(8, 64), (8, 128), (16, 128), (16, 256), (24, 256), (32, 256), (32, 512),
+              (48, 512), (48, 1024)]
+    for tile, threads in shapes:
+        b = gpu_box(gpu_lib, **CONFIG2, schedule="simple")
+        b.set_schedule("fused", tile, threads)
+        b.set_graphs(0 if tile == 24 else 4)
+        b.sweep(20)
+        for a, c in zip(rc, b.cells()):
+            assert np.array_equal(a, c), (tile, threads)
+
+
+def test_graph_replay_matches_eager(gpu_lib):
+    a = gpu_box(gpu_lib, **CONFIG1, schedule="fused", tile=8)
+    b = gpu_box(gpu_lib, **CONFIG1, schedule="fused", tile=8)
+    b.set_graphs(0)
+    a.sweep(3)          # odd start: eager sweeps until the buffers line up
+    a.sweep(300)        # graph replays of 128 sweeps
+    a.sweep(1)
+    for _ in range(304):
+        b.sweep(1)
+    for x, y in zip(a.cells(), b.cells()):
+        assert np.array_equal(x, y)
+    assert a.info()["trials"] == b.info()["trials"]
+
+
+def test_checkpoint_resume_bit_exact(gpu_lib, tmp_path):
+    a = gpu_box(gpu_lib, **CONFIG1)
+    a.sweep(50)
+    a.accumulate_contacts()
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.sweep(70)
+    b = gpu_lib.Box.load(path)
+    b.sweep(70)
+    for x, y in zip(a.cells(), b.cells()):
+        assert np.array_equal(x, y)
+    assert a.info()["sweep"] == b.info()["sweep"] == 120
+    assert np.array_equal(a.contacts()[0], b.contacts()[0])
+
+
+def test_contact_histogram_counts_identical(gpu_lib):
+    g = gpu_box(gpu_lib, **CONFIG1, hist_bins=20, hist_dr=0.01)
+    o = OracleBox(**CONFIG1)
+    oc = np.zeros(20, np.int64)
+    for _ in range(5):
+        g.sweep(37)
+        o.sweep(37)
+        g.accumulate_contacts()
+        o.pair_hist(20, 0.01, oc)
+    gc, n = g.contacts()
+    assert n == 5 and np.array_equal(gc, oc)
+    res = g.measure_pressure()
+    ref = orc.pressure_fit(oc, 0.01, 5, 256, o.info()["L_eff"])
+    assert abs(res["P_star"] - ref["P_star"]) < 1e-10 * ref["P_star"]
+    assert abs(res["g_contact"] - ref["g_contact"]) < 1e-10 * ref["g_contact"]
+
+
+def test_contact_histogram_config2_default_bins(gpu_lib):
+    g = gpu_box(gpu_lib, **CONFIG2)
+    o = OracleBox(**CONFIG2)
+    g.sweep(30)
+    o.sweep(30)
+    g.accumulate_contacts()
+    gc, _ = g.contacts()
+    oc = o.pair_hist(100, 1e-3)
+    assert np.array_equal(gc, oc)
+    assert gc.sum() > 1000
+
+
+def test_psi6_matches_oracle(gpu_lib):
+    g = gpu_box(gpu_lib, **CONFIG1)
+    o = OracleBox(**CONFIG1)
+    g.sweep(200)
+    o.sweep(200)
+    psi, field, Psi = g.psi6_field()
+    opsi = o.psi6()
+    assert np.abs(psi - opsi).max() < 1e-5
+    assert abs(Psi - opsi.mean()) < 1e-6
+    ofield = o.psi6_field(opsi)
+    assert np.abs(field - ofield).max() < 1e-5
+
+
+def test_fused_tiles_must_not_wrap(gpu_lib):
+    """A tile whose halo region would cover the box twice is refused."""
+    g = gpu_box(gpu_lib, **CONFIG1, schedule="simple")
+    with pytest.raises(gpu_lib.MPMCError):
+        g.set_schedule("fused", 16, 256)   # 16 + 2 * 4 > M = 18
+
+
+def test_n2_edge_case_bit_exact(gpu_lib):
+    """Two disks in a 4 x 4 grid: the degenerate box (no fused tile fits)."""
+    g = gpu_lib.Box(2, 0.05, seed=3, step_m=255, lattice="none")
+    o = OracleBox(2, 0.05, seed=3, lattice=2, step_m=255)
+    X = np.array([int(1.0 / orc.Q), int(5.5 / orc.Q)], np.int64)
+    Y = np.array([int(1.0 / orc.Q), int(6.0 / orc.Q)], np.int64)
+    g.set_positions_q(X, Y)
+    o.set_positions_q(X, Y)
+    assert g.info()["schedule"] == 1
+    g.sweep(5000)
+    o.sweep(5000)
+    assert_same_state(g, o)
+
+
+def test_full_size_parity_sampled(gpu_lib):
+    """N = 1024^2 at eta = 0.716 in the benchmark's launch configuration:
+    cell lists after 3 sweeps bit for bit, then sampled observables."""
+    cfg = dict(N=1024 * 1024, eta=0.716, seed=0, lattice=1, step_m=20)
+    g = gpu_box(gpu_lib, **cfg)
+    o = OracleBox(**cfg)
+    g.sweep(3)
+    o.sweep(3)
+    assert_same_state(g, o)
+    rng = np.random.default_rng(0)
+    sel = np.zeros(cfg["N"], np.uint8)
+    sel[rng.choice(cfg["N"], 800, replace=False)] = 1
+    assert np.array_equal(g.contact_hist_subset(sel), o.pair_hist_subset(sel, 100, 1e-3))
+    psi, _, _ = g.psi6_field()
+    opsi = o.psi6(sel)
+    idx = np.nonzero(sel)[0]
+    assert np.abs(psi[idx] - opsi[idx]).max() < 1e-5
+    assert g.validate() == (0, 0)
+
+
+def test_gpu_n2_closed_form_pressure(gpu_lib):
+    """Statistical pin of the GPU sampler itself: for N = 2 the separation is
+    uniform outside the excluded disk, so P* = (4 eta/pi)(1-eta)/(1-2 eta)."""
+    g = gpu_lib.Box(2, 0.05, seed=17, step_m=255, lattice="none", hist_bins=100, hist_dr=0.01,
+                    hist_block=4000)
+    X = np.array([int(1.0 / orc.Q), int(5.5 / orc.Q)], np.int64)
+    Y = np.array([int(1.0 / orc.Q), int(6.0 / orc.Q)], np.int64)
+    g.set_positions_q(X, Y)
+    for _ in range(80000):
+        g.sweep(3)
+        g.accumulate_contacts()
+    eta = g.info()["eta_eff"]
+    res = g.measure_pressure()
+    exact = 4 * eta / math.pi * (1 - eta) / (1 - 2 * eta)
+    assert abs(res["P_star"] - exact) < 3 * res["se"], (res, exact)
