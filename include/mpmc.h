@@ -207,6 +207,41 @@ int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t thr
  * 128 fused / 32 simple); 0 launches every sweep directly. */
 int mpmc_set_graphs(mpmc_box b, uint32_t sweeps_per_graph);
 
+/* ---- batches of independent boxes ----------------------------------------
+ * Many boxes of different N and eta swept together: every sweep of the
+ * batch is one persistent kernel launch whose workgroups stride over a
+ * (box, tile) work list, and runs of sweeps replay a captured HIP graph.
+ * Box b evolves exactly as a single box created with N[b], eta[b], seed[b]
+ * and the same params would (independent Philox keys and geometry).
+ * Error bars from independent runs are how the paper quotes its pressures
+ * (Table I); a batch of seeds provides them in one launch per sweep. */
+typedef struct mpmc_batch_s *mpmc_batch;
+
+/* Creates nbox boxes (1 <= nbox < 4096) from host arrays N, eta, seed and
+ * common params (lattice start, step, trials, histogram; no allocator hook).
+ * The fused tile shape is autotuned over the shapes that fit every box,
+ * unless p->tile is set or p->schedule is MPMC_SCHED_SIMPLE. */
+int mpmc_batch_create(mpmc_batch *out, uint32_t nbox, const uint32_t *N, const double *eta,
+                      const uint64_t *seed, const mpmc_params *p);
+int mpmc_batch_free(mpmc_batch b);
+/* k sweeps of every box; counts (if non-NULL) are summed over boxes. */
+int mpmc_batch_sweep(mpmc_batch b, uint64_t k, uint64_t *trials, uint64_t *accepts);
+/* Borrowed handle of box i for the single-box read and measurement calls
+ * (mpmc_get_*, mpmc_psi6_field, mpmc_accumulate_contacts, ...).  It must not
+ * be swept or freed on its own (MPMC_ESTATE). */
+int mpmc_batch_box(mpmc_batch b, uint32_t i, mpmc_box *out);
+/* Contact histogram of every box; per-box P* and standard error (arrays of
+ * nbox, either may be NULL), as mpmc_measure_pressure. */
+int mpmc_batch_accumulate_contacts(mpmc_batch b);
+int mpmc_batch_measure_pressure(mpmc_batch b, double *p_star, double *se);
+/* Tile shape: (tile, threads) as for mpmc_set_schedule; (0, 0) autotunes;
+ * (0, 1) runs each box with the simple per-colour kernels. */
+int mpmc_batch_set_schedule(mpmc_batch b, uint32_t tile, uint32_t threads);
+int mpmc_batch_info(mpmc_batch b, uint32_t *nbox, uint32_t *tile, uint32_t *threads,
+                    uint32_t *n_items);
+/* Sweeps per captured graph (even, > 0; default 64). */
+int mpmc_batch_set_graphs(mpmc_batch b, uint32_t sweeps_per_graph);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *mpmc_last_error(void);
 

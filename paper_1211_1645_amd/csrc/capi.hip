@@ -408,7 +408,8 @@ extern "C" int mpmc_init_box(mpmc_box *out, uint32_t N, double eta, uint64_t see
 extern "C" int mpmc_free_box(mpmc_box bh) {
     if (!bh) return MPMC_OK;
     Box *b = reinterpret_cast<Box *>(bh);
-    hipStreamSynchronize(b->stream);
+    if (b->in_batch) return fail(MPMC_ESTATE, "this box belongs to a batch; free the batch");
+    (void)hipStreamSynchronize(b->stream);
     b->release();
     delete b;
     return MPMC_OK;
@@ -447,6 +448,7 @@ extern "C" int mpmc_set_step(mpmc_box bh, uint32_t step_m) {
 extern "C" int mpmc_sweep(mpmc_box bh, uint64_t k, uint64_t *trials, uint64_t *accepts) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (b->in_batch) return fail(MPMC_ESTATE, "boxes of a batch are swept with mpmc_batch_sweep");
     DevScalars before;
     if (trials || accepts) {
         int rc = b->read_scalars();

@@ -61,6 +61,7 @@ struct Box {
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_key = 0;
     uint64_t host_sweeps = 0;
+    bool in_batch = false;  // owned by a batch: swept and freed by it
     std::vector<void *> allocations;
 
     int alloc_dev(void **ptr, size_t bytes);

@@ -39,6 +39,15 @@ struct FusedShape { uint32_t tile, threads; };
 bool fused_supported(const BoxView &v, const FusedShape &s);
 const FusedShape *fused_shapes(uint32_t *count);
 void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st);
+// views[2 b + parity]: box b read from buffer `parity`; items: box << 20 | tile
+void launch_fused_batch(const BoxView *views, const uint32_t *items, uint32_t n_items,
+                        uint32_t parity, uint32_t offset, const FusedShape &s, hipStream_t st);
+struct AdvanceDesc {
+    DevScalars *dev;
+    uint32_t seed_lo, seed_hi, W;
+    long long Lq;
+};
+void launch_advance_batch(const AdvanceDesc *desc, uint32_t nbox, uint32_t count, hipStream_t st);
 
 // measure.hip
 struct MeasureView {

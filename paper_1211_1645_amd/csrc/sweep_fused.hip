@@ -186,19 +186,12 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const BoxView &v, const P
     }
 }
 
+// The work of one tile: re-bin, four colour passes, write-back, counts.
 template <int TILE, int THREADS>
-__global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint32_t nty,
-                                                   uint32_t per_xcd) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
+__device__ __forceinline__ void fused_tile(Lds<TILE> &L, const BoxView &v, uint32_t I0,
+                                           uint32_t J0) {
     constexpr int R = Lds<TILE>::R;
     const uint32_t M = v.M;
-
-    // Consecutive workgroups go to different XCDs; give each XCD a
-    // contiguous run of tiles so that shared halo cells meet in its L2.
-    const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
-    if (tile >= ntx * nty) return;
-    const uint32_t I0 = (tile % ntx) * TILE, J0 = (tile / ntx) * TILE;
     const int own_x = (M - I0 < (uint32_t)TILE) ? (int)(M - I0) : TILE;
     const int own_y = (M - J0 < (uint32_t)TILE) ? (int)(M - J0) : TILE;
 
@@ -351,6 +344,37 @@ __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint
     count_trials(v.dev, trials, accepts);
 }
 
+template <int TILE, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint32_t nty,
+                                                   uint32_t per_xcd) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
+    // Consecutive workgroups go to different XCDs; give each XCD a
+    // contiguous run of tiles so that shared halo cells meet in its L2.
+    const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
+    if (tile >= ntx * nty) return;
+    fused_tile<TILE, THREADS>(L, v, (tile % ntx) * TILE, (tile / ntx) * TILE);
+}
+
+// Persistent form for a batch of independent boxes: workgroups stride over
+// a work list of (box, tile) items, item = box << 20 | tile.  All boxes of a
+// batch advance in step, so one buffer parity serves them all.
+template <int TILE, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *views,
+                                                         const uint32_t *items, uint32_t n_items,
+                                                         uint32_t parity, uint32_t offset) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint32_t item = items[it], box = item >> 20, tile = item & 0xFFFFFu;
+        BoxView v = views[2 * box + parity];
+        v.offset = offset;
+        const uint32_t ntx = (v.M + TILE - 1) / TILE;
+        fused_tile<TILE, THREADS>(L, v, (tile % ntx) * TILE, (tile / ntx) * TILE);
+        __syncthreads();
+    }
+}
+
 namespace {
 template <int TILE, int THREADS>
 void launch_t(const BoxView &v, hipStream_t st) {
@@ -366,16 +390,40 @@ void launch_t(const BoxView &v, hipStream_t st) {
     k_fused<TILE, THREADS><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd);
 }
 
+template <int TILE, int THREADS>
+void launch_batch_t(const BoxView *views, const uint32_t *items, uint32_t n_items, uint32_t grid,
+                    uint32_t parity, uint32_t offset, hipStream_t st) {
+    const size_t lds = sizeof(Lds<TILE>);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_fused_batch<TILE, THREADS>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    k_fused_batch<TILE, THREADS><<<grid, THREADS, lds, st>>>(views, items, n_items, parity, offset);
+}
+
+template <int TILE, int THREADS>
+int occupancy_t() {
+    int blocks = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fused_batch<TILE, THREADS>, THREADS,
+                                                       sizeof(Lds<TILE>));
+    return blocks;
+}
+
 struct Entry {
     uint32_t tile, threads;
     void (*fn)(const BoxView &, hipStream_t);
+    void (*batch)(const BoxView *, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t,
+                  hipStream_t);
+    int (*occ)();
 };
 const Entry kShapes[] = {
-    {8, 64, launch_t<8, 64>},       {8, 128, launch_t<8, 128>},
-    {16, 128, launch_t<16, 128>},   {16, 256, launch_t<16, 256>},
-    {24, 256, launch_t<24, 256>},   {32, 256, launch_t<32, 256>},
-    {32, 512, launch_t<32, 512>},   {48, 512, launch_t<48, 512>},
-    {48, 1024, launch_t<48, 1024>}, {56, 1024, launch_t<56, 1024>},
+    {8, 64, launch_t<8, 64>, launch_batch_t<8, 64>, occupancy_t<8, 64>},       {8, 128, launch_t<8, 128>, launch_batch_t<8, 128>, occupancy_t<8, 128>},
+    {16, 128, launch_t<16, 128>, launch_batch_t<16, 128>, occupancy_t<16, 128>},   {16, 256, launch_t<16, 256>, launch_batch_t<16, 256>, occupancy_t<16, 256>},
+    {24, 256, launch_t<24, 256>, launch_batch_t<24, 256>, occupancy_t<24, 256>},   {32, 256, launch_t<32, 256>, launch_batch_t<32, 256>, occupancy_t<32, 256>},
+    {32, 512, launch_t<32, 512>, launch_batch_t<32, 512>, occupancy_t<32, 512>},   {48, 512, launch_t<48, 512>, launch_batch_t<48, 512>, occupancy_t<48, 512>},
+    {48, 1024, launch_t<48, 1024>, launch_batch_t<48, 1024>, occupancy_t<48, 1024>}, {56, 1024, launch_t<56, 1024>, launch_batch_t<56, 1024>, occupancy_t<56, 1024>},
 };
 }  // namespace
 
@@ -395,6 +443,22 @@ bool fused_supported(const BoxView &v, const FusedShape &s) {
     for (const Entry &e : kShapes)
         if (e.tile == s.tile && e.threads == s.threads) return true;
     return false;
+}
+
+void launch_fused_batch(const BoxView *views, const uint32_t *items, uint32_t n_items,
+                        uint32_t parity, uint32_t offset, const FusedShape &s, hipStream_t st) {
+    for (const Entry &e : kShapes)
+        if (e.tile == s.tile && e.threads == s.threads) {
+            int dev = 0, cus = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            const int per_cu = e.occ() > 0 ? e.occ() : 1;
+            uint32_t grid = (uint32_t)(cus > 0 ? cus : 256) * (uint32_t)per_cu;
+            if (grid > n_items) grid = n_items;
+            if (grid == 0) return;
+            e.batch(views, items, n_items, grid, parity, offset, st);
+            return;
+        }
 }
 
 void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st) {

@@ -128,6 +128,27 @@ __global__ void k_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, u
     dev->sweep = s + count;
 }
 
+// The same for every box of a batch, one thread per box.
+__global__ void k_advance_batch(const AdvanceDesc *desc, uint32_t nbox, uint32_t count) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const AdvanceDesc a = desc[b];
+    unsigned long long s = a.dev->sweep;
+    long long Sx = a.dev->Sx, Sy = a.dev->Sy;
+    for (uint32_t g = 0; g < count; ++g) {
+        const SweepDraws d = sweep_draws(a.seed_lo, a.seed_hi, s + g, a.W);
+        Sx = (Sx + d.kx) % a.Lq;
+        Sy = (Sy + d.ky) % a.Lq;
+    }
+    a.dev->Sx = Sx;
+    a.dev->Sy = Sy;
+    a.dev->sweep = s + count;
+}
+
+void launch_advance_batch(const AdvanceDesc *desc, uint32_t nbox, uint32_t count, hipStream_t st) {
+    k_advance_batch<<<(nbox + 63) / 64, 64, 0, st>>>(desc, nbox, count);
+}
+
 void launch_simple_sweep(const BoxView &v, hipStream_t st) {
     const uint32_t nc = v.M * v.M;
     k_rebin<<<(nc + 255) / 256, 256, 0, st>>>(v);

@@ -75,6 +75,16 @@ _SIGS = {
                  C.POINTER(C.c_double)],
     "mpmc_set_schedule": [_P, C.c_uint32, C.c_uint32, C.c_uint32],
     "mpmc_set_graphs": [_P, C.c_uint32],
+    "mpmc_batch_create": [C.POINTER(C.c_void_p), C.c_uint32, _P, _P, _P, C.POINTER(Params)],
+    "mpmc_batch_free": [_P],
+    "mpmc_batch_sweep": [_P, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+    "mpmc_batch_box": [_P, C.c_uint32, C.POINTER(C.c_void_p)],
+    "mpmc_batch_accumulate_contacts": [_P],
+    "mpmc_batch_measure_pressure": [_P, _P, _P],
+    "mpmc_batch_set_schedule": [_P, C.c_uint32, C.c_uint32],
+    "mpmc_batch_info": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                        C.POINTER(C.c_uint32)],
+    "mpmc_batch_set_graphs": [_P, C.c_uint32],
 }
 
 
@@ -183,7 +193,18 @@ class Box:
         cls.__init__(b, 0, 0.0, _handle=h)
         return b
 
+    @classmethod
+    def _borrowed(cls, handle, owner):
+        b = cls.__new__(cls)
+        b._alloc = None
+        b._owner = owner  # keeps the batch alive while the view exists
+        cls.__init__(b, 0, 0.0, _handle=handle)
+        return b
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self.h = None
+            return
         if getattr(self, "h", None) is not None and _lib is not None:
             _lib.mpmc_free_box(self.h)
             self.h = None
@@ -305,6 +326,66 @@ class Box:
 
     def save(self, path):
         _check(_lib.mpmc_save(self.h, path.encode()))
+
+
+class Batch:
+    """Independent boxes (lists N, eta, seed) swept together, one persistent
+    launch per sweep."""
+
+    def __init__(self, N, eta, seed, step_m=26, n_trial=1, lattice="triangular", cell_min=2.0,
+                 hist_dr=1e-3, hist_bins=100, fit_order=4, hist_block=0, schedule="auto", tile=0,
+                 stream=None):
+        lib = load()
+        N = np.ascontiguousarray(N, np.uint32)
+        eta = np.ascontiguousarray(eta, np.float64)
+        seed = np.ascontiguousarray(seed, np.uint64)
+        assert len(N) == len(eta) == len(seed)
+        p = Box._params(self, step_m, n_trial, lattice, cell_min, hist_dr, hist_bins, fit_order,
+                        hist_block, schedule, tile, stream, False)
+        h = C.c_void_p()
+        _check(lib.mpmc_batch_create(C.byref(h), len(N), _ptr(N), _ptr(eta), _ptr(seed), C.byref(p)))
+        self.h = h
+        self.n = len(N)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.mpmc_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def sweep(self, k=1, counts=False):
+        if counts:
+            t, a = C.c_uint64(), C.c_uint64()
+            _check(_lib.mpmc_batch_sweep(self.h, k, C.byref(t), C.byref(a)))
+            return t.value, a.value
+        _check(_lib.mpmc_batch_sweep(self.h, k, None, None))
+
+    def box(self, i):
+        h = C.c_void_p()
+        _check(_lib.mpmc_batch_box(self.h, i, C.byref(h)))
+        return Box._borrowed(h, self)
+
+    def accumulate_contacts(self):
+        _check(_lib.mpmc_batch_accumulate_contacts(self.h))
+
+    def measure_pressure(self):
+        P = np.zeros(self.n, np.float64)
+        se = np.zeros(self.n, np.float64)
+        _check(_lib.mpmc_batch_measure_pressure(self.h, _ptr(P), _ptr(se)))
+        return P, se
+
+    def set_schedule(self, tile=0, threads=0):
+        _check(_lib.mpmc_batch_set_schedule(self.h, tile, threads))
+
+    def set_graphs(self, sweeps_per_graph):
+        _check(_lib.mpmc_batch_set_graphs(self.h, sweeps_per_graph))
+
+    def info(self):
+        n, t, th, it = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(_lib.mpmc_batch_info(self.h, C.byref(n), C.byref(t), C.byref(th), C.byref(it)))
+        return dict(nbox=n.value, tile=t.value, threads=th.value, n_items=it.value)
 
 
 def acf(series, maxlag):
