@@ -242,6 +242,64 @@ int mpmc_batch_info(mpmc_batch b, uint32_t *nbox, uint32_t *tile, uint32_t *thre
 /* Sweeps per captured graph (even, > 0; default 64). */
 int mpmc_batch_set_graphs(mpmc_batch b, uint32_t sweeps_per_graph);
 
+/* ---- learned proposal ------------------------------------------------------
+ * An extension of the uniform trial move of Sec. II.B: a small network maps
+ * the moving disk's neighbourhood to a displacement density, and a
+ * Metropolis-Hastings correction keeps every trial exact.
+ *  features: the up to 12 nearest other disks within 3 sigma of the disk's
+ *    position, as (dx, dy) pairs sorted by fp32 r^2 (ties: enumeration order
+ *    over the 3 x 3 cell block, rows dj = -1..1 outer, columns inner, slots
+ *    ascending), zero padded to 24 floats.
+ *  network: 24 -> 64 -> 64 -> 20 with SiLU; parameters (7060 floats) in the
+ *    order W1[64][24], b1[64], W2[64][64], b2[64], W3[20][64], b3[20];
+ *    output k (0..3) = (logit, mu_x, mu_y, a_x, a_y) at 5k..5k+4, component
+ *    width exp(clamp(a, -7, 1)); BF16 weights, FP32 accumulation.
+ *  proposal: q(delta) = eps U(delta) + (1 - eps) sum_k pi_k N(delta; mu_k,
+ *    diag(s_k^2)), U uniform over the lattice steps in [-d, d]^2; delta is
+ *    rounded to the q lattice.
+ *  acceptance: min(1, q(-delta | f(x')) / q(delta | f(x))) if x' stays in
+ *    its cell and overlaps no disk.
+ * Boxes swept with the learned proposal need cells of width >= 3 sigma
+ * (mpmc_params.cell_min = 3): the 3 sigma neighbourhoods of x and x' then
+ * lie in cells that no other thread moves during the colour sub-sweep. */
+#define MPMC_MLP_PARAMS 7060
+typedef struct mpmc_learner_s *mpmc_learner;
+
+/* Creates a network with default weights (uniform +-1/sqrt(fan_in) from
+ * Philox words of `seed`) and room for `capacity` recorded moves; stream is
+ * a hipStream_t (NULL = default). */
+int mpmc_learner_create(mpmc_learner *out, uint64_t seed, uint64_t capacity, void *stream);
+int mpmc_learner_free(mpmc_learner l);
+/* Host arrays of MPMC_MLP_PARAMS floats; setting resets the Adam state. */
+int mpmc_learner_set_params(mpmc_learner l, const float *params);
+int mpmc_learner_get_params(mpmc_learner l, float *params);
+/* Runs `sweeps` plain sweeps of box b (cell_min >= 3; same trajectory as
+ * mpmc_sweep with the simple schedule) and records every accepted move as
+ * (features at the old position, delta).  *n_total: moves recorded so far
+ * (at most capacity). */
+int mpmc_learner_collect(mpmc_learner l, mpmc_box b, uint64_t sweeps, uint64_t *n_total);
+/* `steps` Adam steps (lr; beta 0.9/0.999) on minibatches of `batch` moves
+ * drawn with replacement by Philox; loss = mean -log q_GMM(delta | f).
+ * *mean_loss: the loss of the last minibatch. */
+int mpmc_learner_train(mpmc_learner l, uint32_t steps, uint32_t batch, float lr, double *mean_loss);
+/* Diagnostics on host arrays: network outputs out[B][20] for F[B][24];
+ * the gradient (MPMC_MLP_PARAMS floats) and value of the mean loss over the
+ * moves (F[B][24], D[B][2]). */
+int mpmc_learner_forward(mpmc_learner l, const float *F, uint32_t B, float *out);
+int mpmc_learner_nll_grad(mpmc_learner l, const float *F, const float *D, uint32_t B, float *grad,
+                          double *loss);
+/* Moves recorded, neighbourhoods seen with more than 12 disks within 3
+ * sigma (impossible for valid configurations), training steps done. */
+int mpmc_learner_info(mpmc_learner l, uint64_t *n_data, uint64_t *n_feature_overflow,
+                      uint32_t *steps);
+/* Features of the disks with the given tags at their current positions,
+ * F[n][24] (host). */
+int mpmc_learned_features(mpmc_box b, const uint32_t *tags, uint32_t n, float *F);
+/* k sweeps with the learned proposal (eps in [0, 1] is the weight of the
+ * uniform fallback); counts as mpmc_sweep. */
+int mpmc_sweep_learned(mpmc_box b, mpmc_learner l, uint64_t k, float eps, uint64_t *trials,
+                       uint64_t *accepts);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *mpmc_last_error(void);
 

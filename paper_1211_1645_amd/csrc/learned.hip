@@ -1,0 +1,1130 @@
+// learned.hip — a learned local proposal for the MPMC sweep, kept exact by a
+// Metropolis-Hastings correction (an extension of the paper's uniform trial
+// move of Sec. II.B; the uniform move stays in the mixture as fallback).
+//
+//  features  f(x): the up to 12 nearest other disks within 3 sigma of the
+//            trial position, (dx, dy) each, sorted by (fp32 r^2, enumeration
+//            order over the 3 x 3 cell block), zero padded to 24.
+//  network   24 -> 64 -> 64 -> 20, SiLU, BF16 weights with FP32 accumulate
+//            on the matrix cores (v_mfma_f32_16x16x16bf16), the 64 lanes of
+//            a wave forming the GEMM row dimension.
+//  proposal  q(delta | f) = eps U_d(delta) + (1 - eps) sum_k pi_k
+//            N(delta; mu_k, diag(s_k^2)), 4 components, s = exp(clamp(a)).
+//  MH        accept with min(1, q(-delta | f(x')) / q(delta | f(x))) if x'
+//            stays in the cell and overlaps nothing.  Cells of width >= 3
+//            sigma keep the 3 sigma neighbourhoods of x and x' frozen while a
+//            colour sub-sweep runs, so each trial is an exact MH step.
+//  training  accepted plain moves (f(x), delta) are recorded; the network
+//            is trained to maximise log q_GMM(delta | f) with the same MFMA
+//            GEMMs run forward and backward, and Adam on FP32 master weights.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "mpmc_host.hpp"
+
+namespace mpmc {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kNF = 24, kNH = 64, kNO = 20, kNPARAM = 7060;
+constexpr int kPW1 = 0, kPB1 = kPW1 + 64 * 24, kPW2 = kPB1 + 64, kPB2 = kPW2 + 64 * 64,
+              kPW3 = kPB2 + 64, kPB3 = kPW3 + 20 * 64;
+constexpr int kStreamTrain = 5;
+
+// BF16 weights in the layouts the GEMMs read (k contiguous), zero padded:
+// w1[64 out][32 in], w2[64][64], w3[32 out][64 in] and, for the backward
+// pass, w2t[64 in][64 out], w3t[64 in][32 out].
+struct PackedW {
+    uint16_t w1[64 * 32];
+    uint16_t w2[64 * 64];
+    uint16_t w3[32 * 64];
+    uint16_t w2t[64 * 64];
+    uint16_t w3t[64 * 32];
+    float b1[64], b2[64], b3[32];
+};
+// The part the inference kernels load into LDS.
+struct PackedWInfer {
+    uint16_t w1[64 * 32];
+    uint16_t w2[64 * 64];
+    uint16_t w3[32 * 64];
+    float b1[64], b2[64], b3[32];
+};
+
+__host__ __device__ inline uint16_t f2bf(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline float silu(float v) { return v / (1.0f + __expf(-v)); }
+__device__ inline float dsilu(float v) {
+    const float s = 1.0f / (1.0f + __expf(-v));
+    return s * (1.0f + v * (1.0f - s));
+}
+
+// All 64 lanes of the wave see each other's LDS writes after this.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// acc[mi][ni] += A[16 mi.., :] Bt[16 ni.., :]^T over K = 16 KT, with A and
+// Bt bf16 row-major in LDS (k contiguous).  Lane l holds, for the 16 x 16 x
+// 16 MFMA, A[row l%16][k = 4(l/16)..+3], B[k = 4(l/16)..+3][col l%16] and
+// C[rows 4(l/16)..+3][col l%16].
+template <int MT, int NT, int KT>
+__device__ inline void wave_gemm(const uint16_t *A, int lda, const uint16_t *Bt, int ldb,
+                                 v4f (&acc)[MT][NT]) {
+    const int l = threadIdx.x & 63, r = l & 15, kg = (l >> 4) * 4;
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+        v4s a[MT], b[NT];
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+            a[mi] = *reinterpret_cast<const v4s *>(A + (16 * mi + r) * lda + 16 * ks + kg);
+#pragma unroll
+        for (int ni = 0; ni < NT; ++ni)
+            b[ni] = *reinterpret_cast<const v4s *>(Bt + (16 * ni + r) * ldb + 16 * ks + kg);
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NT; ++ni)
+                acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+}
+
+template <int MT, int NT>
+__device__ inline void zero_acc(v4f (&acc)[MT][NT]) {
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+// Forward pass of one wave: X[64][32] -> H1, H2 -> OUT[64][32] (fp32; the
+// 20 outputs in columns 0..19).  If A1/A2 are given the pre-activations are
+// kept (fp32 [64][64]) and transposed bf16 copies of X, H1, H2 are written
+// for the backward pass.
+struct FwdBufs {
+    uint16_t *X, *H1, *H2;       // row-major bf16
+    uint16_t *XT, *H1T, *H2T;    // transposed bf16 (training only)
+    float *A1, *A2;              // pre-activations (training only)
+    float *OUT;                  // [64][32]
+};
+
+template <class WT>
+__device__ inline void mlp_forward_wave(const WT &W, const FwdBufs &B) {
+    const int l = threadIdx.x & 63, col = l & 15, rg = (l >> 4) * 4;
+    {
+        v4f acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4, 4, 2>(B.X, 32, W.w1, 32, acc);
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 16 * mi + rg + e, n = 16 * ni + col;
+                    const float a = acc[mi][ni][e] + W.b1[n];
+                    const uint16_t h = f2bf(silu(a));
+                    B.H1[m * 64 + n] = h;
+                    if (B.A1) {
+                        B.A1[m * 64 + n] = a;
+                        B.H1T[n * 64 + m] = h;
+                    }
+                }
+    }
+    wave_sync();
+    {
+        v4f acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4, 4, 4>(B.H1, 64, W.w2, 64, acc);
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 16 * mi + rg + e, n = 16 * ni + col;
+                    const float a = acc[mi][ni][e] + W.b2[n];
+                    const uint16_t h = f2bf(silu(a));
+                    B.H2[m * 64 + n] = h;
+                    if (B.A2) {
+                        B.A2[m * 64 + n] = a;
+                        B.H2T[n * 64 + m] = h;
+                    }
+                }
+    }
+    wave_sync();
+    {
+        v4f acc[4][2];
+        zero_acc(acc);
+        wave_gemm<4, 2, 4>(B.H2, 64, W.w3, 64, acc);
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 16 * mi + rg + e, n = 16 * ni + col;
+                    B.OUT[m * 32 + n] = acc[mi][ni][e] + W.b3[n];
+                }
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Mixture density and sampling (one lane, one sample).
+struct Gmm {
+    float lw[4], mx[4], my[4], ax[4], ay[4];
+};
+
+__device__ inline float clampa(float a) { return fminf(fmaxf(a, -7.0f), 1.0f); }
+
+__device__ inline Gmm gmm_from(const float *o) {
+    Gmm g;
+    float mx = o[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) mx = fmaxf(mx, o[5 * k]);
+    float z = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z += expf(o[5 * k] - mx);
+    const float lz = logf(z) + mx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        g.lw[k] = o[5 * k] - lz;
+        g.mx[k] = o[5 * k + 1];
+        g.my[k] = o[5 * k + 2];
+        g.ax[k] = clampa(o[5 * k + 3]);
+        g.ay[k] = clampa(o[5 * k + 4]);
+    }
+    return g;
+}
+
+__device__ inline float log_gmm(const Gmm &g, float dx, float dy) {
+    float l[4], best = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float ux = (dx - g.mx[k]) * expf(-g.ax[k]), uy = (dy - g.my[k]) * expf(-g.ay[k]);
+        l[k] = g.lw[k] - 1.8378770664093453f - g.ax[k] - g.ay[k] - 0.5f * (ux * ux + uy * uy);
+        best = fmaxf(best, l[k]);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += expf(l[k] - best);
+    return best + logf(s);
+}
+
+// log q(delta) of the defensive mixture; the uniform part is the discrete
+// uniform law over the (2 D + 1)^2 lattice steps in [-d, d]^2 divided by q^2.
+__device__ inline float log_q(const Gmm &g, float dx, float dy, int Dx, int Dy, int Dm, float eps,
+                              float log_u) {
+    const float lg = logf(1.0f - eps) + log_gmm(g, dx, dy);
+    if (abs(Dx) > Dm || abs(Dy) > Dm || eps <= 0.0f) return lg;
+    const float lu = logf(eps) + log_u;
+    const float mx = fmaxf(lg, lu);
+    return mx + logf(expf(lg - mx) + expf(lu - mx));
+}
+
+// ---------------------------------------------------------------------------
+// Features of a disk of cell (ci, cj) at cell-local (x, y), slot `self` of
+// the own cell excluded, from the cell lists (cnt, px, py with stride CS).
+// scr: this lane's 36-float scratch.  Writes bf16 into Xrow[0..31] and/or
+// fp32 into Frow[0..23] (either may be NULL).  Returns the neighbour count.
+__device__ inline int lane_features(const uint8_t *cnt, const float *px, const float *py,
+                                    uint32_t M, uint32_t CS, float w, uint32_t ci, uint32_t cj,
+                                    uint32_t self, float x, float y, float *scr, uint16_t *Xrow,
+                                    float *Frow) {
+    int n = 0;
+    const uint32_t own = ci + M * cj;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+            const uint32_t i = (uint32_t)((int)ci + di + (int)M) % M;
+            const uint32_t j = (uint32_t)((int)cj + dj + (int)M) % M;
+            const uint32_t nb = i + M * j;
+            const float cwx = (float)di * w, cwy = (float)dj * w;
+            const uint32_t m = cnt[nb];
+            for (uint32_t s = 0; s < m; ++s) {
+                if (nb == own && s == self) continue;
+                const float dx = (px[nb * CS + s] - x) + cwx;
+                const float dy = (py[nb * CS + s] - y) + cwy;
+                const float r2 = r2_f32(dx, dy);
+                if (!(r2 < 9.0f)) continue;
+                if (n < 12) {
+                    scr[3 * n] = dx;
+                    scr[3 * n + 1] = dy;
+                    scr[3 * n + 2] = r2;
+                }
+                ++n;
+            }
+        }
+    const int nn = n < 12 ? n : 12;
+    if (Xrow)
+        for (int k = 0; k < 32; ++k) Xrow[k] = 0;
+    if (Frow)
+        for (int k = 0; k < 24; ++k) Frow[k] = 0.0f;
+    for (int c = 0; c < nn; ++c) {
+        const float rc = scr[3 * c + 2];
+        int rank = 0;
+        for (int e = 0; e < nn; ++e) {
+            const float re = scr[3 * e + 2];
+            rank += (re < rc || (re == rc && e < c)) ? 1 : 0;
+        }
+        if (Xrow) {
+            Xrow[2 * rank] = f2bf(scr[3 * c]);
+            Xrow[2 * rank + 1] = f2bf(scr[3 * c + 1]);
+        }
+        if (Frow) {
+            Frow[2 * rank] = scr[3 * c];
+            Frow[2 * rank + 1] = scr[3 * c + 1];
+        }
+    }
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// Learned colour sub-sweep: one wave per 64 active cells, every lane running
+// its cell's trials; the two network evaluations of a trial are wave-wide.
+struct LearnView {
+    const PackedW *W;
+    float eps;
+    unsigned long long *nfeat_over;  // neighbourhoods with more than 12 disks
+};
+
+struct LdsLearn {
+    PackedWInfer w;
+    uint16_t X[64 * 32];
+    uint16_t H1[64 * 64];  // also the network output [64][32] fp32 and,
+    uint16_t H2[64 * 64];  // before the network runs, the feature scratch
+};
+
+__global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, LearnView lv) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LdsLearn &L = *reinterpret_cast<LdsLearn *>(lds_raw);
+    const int lane = threadIdx.x;
+    // weights into LDS
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(lv.W);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.w);
+        constexpr uint32_t nw = (64 * 32 + 64 * 64 + 32 * 64) / 2;  // w1, w2, w3 words
+        for (uint32_t k = lane; k < nw; k += 64) dst[k] = src[k];
+        L.w.b1[lane] = lv.W->b1[lane];
+        L.w.b2[lane] = lv.W->b2[lane];
+        if (lane < 32) L.w.b3[lane] = lv.W->b3[lane];
+    }
+    __syncthreads();
+    const uint32_t M = v.M, h = M / 2;
+    const uint32_t t = blockIdx.x * 64 + lane;
+    const uint64_t sweep = v.dev->sweep + v.offset;
+    const SweepDraws sd = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
+    const uint32_t colour = colour_of_pass(sd.perm, pass);
+    const bool valid = t < h * h;
+    const uint32_t ci = valid ? 2 * (t % h) + (colour & 1u) : 0;
+    const uint32_t cj = valid ? 2 * (t / h) + (colour >> 1) : 0;
+    const uint32_t cell = ci + M * cj;
+    const uint32_t n = valid ? v.cnt_out[cell] : 0;
+    const int Dm = (int)v.step_m << 14;  // d in q units
+    const float log_u = -2.0f * logf((float)(2 * Dm + 1) * kQ);
+    float *scr = reinterpret_cast<float *>(L.H1) + 36 * lane;  // scratch before the MLP
+    uint32_t trials = 0, accepts = 0;
+    uint32_t perm = 0x76543210u;
+    if (n > 1 && v.n_trial > 1) {
+        const Words wd = draw(v.seed_lo, v.seed_hi, sweep, cell, 0, kStreamShuffle);
+        const uint32_t wv[4] = {wd.w0, wd.w1, wd.w2, wd.w3};
+        for (uint32_t i = n - 1; i >= 1; --i) {
+            const uint32_t e = n - 1 - i;
+            Words we = wd;
+            if (e >= 4) we = draw(v.seed_lo, v.seed_hi, sweep, cell, e / 4, kStreamShuffle);
+            const uint32_t q4 = e & 3u;
+            const uint32_t word = e < 4 ? wv[e] : (q4 == 0 ? we.w0 : q4 == 1 ? we.w1 : q4 == 2 ? we.w2 : we.w3);
+            const uint32_t jj = mulhi32(word, i + 1);
+            const uint32_t pi = (perm >> (4 * i)) & 0xFu, pj = (perm >> (4 * jj)) & 0xFu;
+            perm &= ~((0xFu << (4 * i)) | (0xFu << (4 * jj)));
+            perm |= (pj << (4 * i)) | (pi << (4 * jj));
+        }
+    }
+    for (uint32_t tr = 0; tr < v.n_trial; ++tr) {
+        const bool act = n > 0;
+        Words w4{0, 0, 0, 0}, w2{0, 0, 0, 0};
+        uint32_t slot = 0;
+        float x = 0.0f, y = 0.0f;
+        if (act) {
+            w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
+            w2 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
+            slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
+            x = v.x_out[cell * v.CS + slot];
+            y = v.y_out[cell * v.CS + slot];
+        }
+        wave_sync();
+        // sorted features into this lane's row of X
+        if (act) {
+            const int nf = lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, x, y,
+                                         scr, L.X + 32 * lane, nullptr);
+            if (nf > 12) atomicAdd(lv.nfeat_over, 1ull);
+        } else {
+            for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = 0;
+        }
+        wave_sync();
+        float *OUT = reinterpret_cast<float *>(L.H1);
+        FwdBufs fb{L.X, L.H1, L.H2, nullptr, nullptr, nullptr, nullptr, nullptr, OUT};
+        mlp_forward_wave(L.w, fb);
+        // propose
+        Gmm g = gmm_from(OUT + 32 * lane);
+        const uint32_t eps_u = (uint32_t)fminf(lv.eps * 4294967296.0f, 4294967295.0f);
+        int Dx, Dy;
+        if (w4.w1 < eps_u) {
+            Dx = (int)mulhi32(w4.w2, 2u * (uint32_t)Dm + 1u) - Dm;
+            Dy = (int)mulhi32(w4.w3, 2u * (uint32_t)Dm + 1u) - Dm;
+        } else {
+            const float uk = (float)(w2.w0 >> 8) * (1.0f / 16777216.0f);
+            int k = 3;
+            float cum = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                cum += expf(g.lw[c]);
+                if (uk < cum) { k = c; break; }
+            }
+            const float u1 = (float)((w2.w1 >> 8) + 1u) * (1.0f / 16777216.0f);
+            const float u2 = (float)(w2.w2 >> 8) * (1.0f / 16777216.0f);
+            const float rr = sqrtf(-2.0f * logf(u1));
+            float sn, cs;
+            sincosf(6.283185307179586f * u2, &sn, &cs);
+            const float ddx = g.mx[k] + expf(g.ax[k]) * rr * cs;
+            const float ddy = g.my[k] + expf(g.ay[k]) * rr * sn;
+            Dx = (int)rintf(fminf(fmaxf(ddx, -1.0f), 1.0f) * 4194304.0f);
+            Dy = (int)rintf(fminf(fmaxf(ddy, -1.0f), 1.0f) * 4194304.0f);
+        }
+        const float dxf = (float)Dx * kQ, dyf = (float)Dy * kQ;
+        const float lq_f = log_q(g, dxf, dyf, Dx, Dy, Dm, lv.eps, log_u);
+        // geometry in q units: exact
+        const int U = (int)(x * 4194304.0f) + Dx, V = (int)(y * 4194304.0f) + Dy;
+        bool ok = act && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
+        const float xn = (float)U * kQ, yn = (float)V * kQ;
+        if (ok) {
+            for (int dj = -1; dj <= 1 && ok; ++dj)
+                for (int di = -1; di <= 1 && ok; ++di) {
+                    const uint32_t i = (uint32_t)((int)ci + di + (int)M) % M;
+                    const uint32_t j = (uint32_t)((int)cj + dj + (int)M) % M;
+                    const uint32_t nb = i + M * j;
+                    const float cwx = (float)di * v.w, cwy = (float)dj * v.w;
+                    const uint32_t m = v.cnt_out[nb];
+                    for (uint32_t s = 0; s < m; ++s) {
+                        if (nb == cell && s == slot) continue;
+                        const float ddx = (v.x_out[nb * v.CS + s] - xn) + cwx;
+                        const float ddy = (v.y_out[nb * v.CS + s] - yn) + cwy;
+                        if (overlap_f32(ddx, ddy)) { ok = false; break; }
+                    }
+                }
+        }
+        // reverse density at x' (every lane takes part in the wave GEMMs)
+        wave_sync();
+        if (ok) {
+            lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, xn, yn, scr,
+                          L.X + 32 * lane, nullptr);
+        } else {
+            for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = 0;
+        }
+        wave_sync();
+        mlp_forward_wave(L.w, fb);
+        if (act) ++trials;
+        if (ok) {
+            const Gmm gr = gmm_from(OUT + 32 * lane);
+            const float lq_r = log_q(gr, -dxf, -dyf, -Dx, -Dy, Dm, lv.eps, log_u);
+            const float ua = ((float)(w2.w3 >> 8) + 0.5f) * (1.0f / 16777216.0f);
+            if (logf(ua) < lq_r - lq_f) {
+                v.x_out[cell * v.CS + slot] = xn;
+                v.y_out[cell * v.CS + slot] = yn;
+                ++accepts;
+            }
+        }
+        wave_sync();
+    }
+    count_trials(v.dev, trials, accepts);
+}
+
+// ---------------------------------------------------------------------------
+// Plain colour sub-sweep that also records accepted moves: (f(x) at the old
+// position, delta) into the data set.  The trajectory is the plain one.
+struct CollectView {
+    float *F;       // [cap][24]
+    float *D;       // [cap][2]
+    unsigned long long *count;
+    uint64_t cap;
+};
+
+__global__ void __launch_bounds__(128) k_pass_collect(BoxView v, uint32_t pass, CollectView cv) {
+    __shared__ float scr_all[128 * 36];
+    float *scr = scr_all + 36 * threadIdx.x;
+    const uint32_t M = v.M, h = M / 2;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t sweep = v.dev->sweep + v.offset;
+    const SweepDraws sd = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
+    const uint32_t colour = colour_of_pass(sd.perm, pass);
+    uint32_t trials = 0, accepts = 0;
+    if (t < h * h) {
+        const uint32_t ci = 2 * (t % h) + (colour & 1u), cj = 2 * (t / h) + (colour >> 1);
+        const uint32_t cell = ci + M * cj;
+        const uint32_t n = v.cnt_out[cell];
+        uint32_t perm = 0x76543210u;
+        if (n > 1 && v.n_trial > 1) {
+            const Words wd = draw(v.seed_lo, v.seed_hi, sweep, cell, 0, kStreamShuffle);
+            const uint32_t wv[4] = {wd.w0, wd.w1, wd.w2, wd.w3};
+            for (uint32_t i = n - 1; i >= 1; --i) {
+                const uint32_t e = n - 1 - i;
+                Words we = wd;
+                if (e >= 4) we = draw(v.seed_lo, v.seed_hi, sweep, cell, e / 4, kStreamShuffle);
+                const uint32_t q4 = e & 3u;
+                const uint32_t word = e < 4 ? wv[e] : (q4 == 0 ? we.w0 : q4 == 1 ? we.w1 : q4 == 2 ? we.w2 : we.w3);
+                const uint32_t jj = mulhi32(word, i + 1);
+                const uint32_t pi = (perm >> (4 * i)) & 0xFu, pj = (perm >> (4 * jj)) & 0xFu;
+                perm &= ~((0xFu << (4 * i)) | (0xFu << (4 * jj)));
+                perm |= (pj << (4 * i)) | (pi << (4 * jj));
+            }
+        }
+        for (uint32_t tr = 0; tr < v.n_trial && n > 0; ++tr) {
+            const Words w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
+            const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
+            const uint32_t k = cell * v.CS + slot;
+            const float dx = step_from_word(w4.w1, v.step_m), dy = step_from_word(w4.w2, v.step_m);
+            const float x = v.x_out[k], y = v.y_out[k];
+            const float xn = x + dx, yn = y + dy;
+            ++trials;
+            if (!(xn >= 0.0f && xn < v.w && yn >= 0.0f && yn < v.w)) continue;
+            bool bad = false;
+            for (int dj = -1; dj <= 1 && !bad; ++dj)
+                for (int di = -1; di <= 1 && !bad; ++di) {
+                    const uint32_t i = (uint32_t)((int)ci + di + (int)M) % M;
+                    const uint32_t j = (uint32_t)((int)cj + dj + (int)M) % M;
+                    const uint32_t nb = i + M * j;
+                    const float cwx = (float)di * v.w, cwy = (float)dj * v.w;
+                    const uint32_t m = v.cnt_out[nb];
+                    for (uint32_t s = 0; s < m; ++s) {
+                        if (nb == cell && s == slot) continue;
+                        const float ddx = (v.x_out[nb * v.CS + s] - xn) + cwx;
+                        const float ddy = (v.y_out[nb * v.CS + s] - yn) + cwy;
+                        if (overlap_f32(ddx, ddy)) { bad = true; break; }
+                    }
+                }
+            if (bad) continue;
+            const unsigned long long idx = atomicAdd(cv.count, 1ull);
+            if (idx < cv.cap) {
+                lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, x, y, scr,
+                              nullptr, cv.F + idx * 24);
+                cv.D[2 * idx] = dx;
+                cv.D[2 * idx + 1] = dy;
+            }
+            v.x_out[k] = xn;
+            v.y_out[k] = yn;
+            ++accepts;
+        }
+    }
+    count_trials(v.dev, trials, accepts);
+}
+
+// Features of selected disks at their current positions (diagnostic): the
+// disk of tag t goes to row row_of[t] (or nowhere if -1).
+__global__ void k_features(const uint8_t *cnt, const float *px, const float *py, const uint32_t *tag,
+                           uint32_t M, uint32_t CS, float w, const int32_t *row_of, float *F) {
+    __shared__ float scr_all[256 * 36];
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t cell = gid / CS, s = gid % CS;
+    if (cell >= M * M || s >= cnt[cell]) return;
+    const int32_t r = row_of[tag[cell * CS + s]];
+    if (r < 0) return;
+    lane_features(cnt, px, py, M, CS, w, cell % M, cell / M, s, px[cell * CS + s], py[cell * CS + s],
+                  scr_all + 36 * threadIdx.x, nullptr, F + (size_t)r * 24);
+}
+
+// ---------------------------------------------------------------------------
+// Training: one wave per 64 samples, forward with saved activations, the
+// gradient of the mean negative log-likelihood, backward GEMMs on the matrix
+// cores, gradients accumulated into an fp32 buffer.
+struct LdsTrain {
+    PackedW w;
+    uint16_t X[64 * 32], XT[32 * 64];
+    uint16_t H1[64 * 64], H1T[64 * 64];
+    uint16_t H2[64 * 64], H2T[64 * 64];
+    float A1[64 * 64], A2[64 * 64];
+    float OUT[64 * 32];
+    uint16_t DO[64 * 32], DOT[32 * 64];
+};
+
+struct TrainView {
+    const PackedW *W;
+    const float *F, *D;           // data set
+    uint64_t n_data;              // samples in the data set
+    const uint32_t *index;        // explicit sample list (or NULL: Philox draws)
+    uint32_t batch;               // samples in this step (mean over these)
+    uint32_t seed_lo, seed_hi;
+    uint32_t step;
+    float *grad;                  // [7060] accumulated
+    double *loss;                 // accumulated sum of NLL
+};
+
+__global__ void __launch_bounds__(64) k_train(TrainView tv) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LdsTrain &L = *reinterpret_cast<LdsTrain *>(lds_raw);
+    const int lane = threadIdx.x, col = lane & 15, rg = (lane >> 4) * 4;
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(tv.W);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.w);
+        for (uint32_t k = lane; k < sizeof(PackedW) / 4; k += 64) dst[k] = src[k];
+    }
+    // this lane's sample
+    const uint32_t sidx = blockIdx.x * 64 + lane;
+    const bool live = sidx < tv.batch;
+    uint64_t di = 0;
+    if (live) {
+        if (tv.index) {
+            di = tv.index[sidx];
+        } else {
+            const Words wd = philox(tv.seed_lo, tv.seed_hi, tv.step, sidx, 0, kStreamTrain);
+            di = (((uint64_t)wd.w0 << 32) | wd.w1) % tv.n_data;
+        }
+    }
+    float f[24];
+    for (int k = 0; k < 24; ++k) f[k] = live ? tv.F[di * 24 + k] : 0.0f;
+    const float ddx = live ? tv.D[2 * di] : 0.0f, ddy = live ? tv.D[2 * di + 1] : 0.0f;
+    for (int k = 0; k < 32; ++k) {
+        const uint16_t b = k < 24 ? f2bf(f[k]) : 0;
+        L.X[32 * lane + k] = b;
+        L.XT[k * 64 + lane] = b;
+    }
+    __syncthreads();
+    FwdBufs fb{L.X, L.H1, L.H2, L.XT, L.H1T, L.H2T, L.A1, L.A2, L.OUT};
+    mlp_forward_wave(L.w, fb);
+    // d(-log q_GMM)/d out for this sample, scaled by 1/batch
+    const float inv = 1.0f / (float)tv.batch;
+    float dout[20];
+    {
+        const float *o = L.OUT + 32 * lane;
+        const Gmm g = gmm_from(o);
+        float l[4], best = -INFINITY, ux[4], uy[4];
+        for (int k = 0; k < 4; ++k) {
+            ux[k] = (ddx - g.mx[k]) * expf(-g.ax[k]);
+            uy[k] = (ddy - g.my[k]) * expf(-g.ay[k]);
+            l[k] = g.lw[k] - 1.8378770664093453f - g.ax[k] - g.ay[k] - 0.5f * (ux[k] * ux[k] + uy[k] * uy[k]);
+            best = fmaxf(best, l[k]);
+        }
+        float s = 0.0f;
+        for (int k = 0; k < 4; ++k) s += expf(l[k] - best);
+        const float lse = best + logf(s);
+        for (int k = 0; k < 4; ++k) {
+            const float r = expf(l[k] - lse), pk = expf(g.lw[k]);
+            const float inx = (o[5 * k + 3] > -7.0f && o[5 * k + 3] < 1.0f) ? 1.0f : 0.0f;
+            const float iny = (o[5 * k + 4] > -7.0f && o[5 * k + 4] < 1.0f) ? 1.0f : 0.0f;
+            dout[5 * k] = (pk - r) * inv;
+            dout[5 * k + 1] = -r * ux[k] * expf(-g.ax[k]) * inv;
+            dout[5 * k + 2] = -r * uy[k] * expf(-g.ay[k]) * inv;
+            dout[5 * k + 3] = -r * (ux[k] * ux[k] - 1.0f) * inx * inv;
+            dout[5 * k + 4] = -r * (uy[k] * uy[k] - 1.0f) * iny * inv;
+        }
+        double nll = live ? -(double)lse : 0.0;
+        for (int off = 32; off > 0; off >>= 1) nll += __shfl_xor(nll, off, 64);
+        if (lane == 0) atomicAdd(tv.loss, nll);
+    }
+    for (int k = 0; k < 32; ++k) {
+        const float gk = (live && k < 20) ? dout[k < 20 ? k : 0] : 0.0f;
+        const uint16_t b = f2bf(gk);
+        L.DO[32 * lane + k] = b;
+        L.DOT[k * 64 + lane] = b;
+    }
+    // db3: sum over the samples
+    for (int k = 0; k < 20; ++k) {
+        float gk = live ? dout[k] : 0.0f;
+        for (int off = 32; off > 0; off >>= 1) gk += __shfl_xor(gk, off, 64);
+        if (lane == 0) atomicAdd(&tv.grad[kPB3 + k], gk);
+    }
+    __syncthreads();
+    // dW3[o][i] = sum_s dOut[s][o] H2[s][i]
+    {
+        v4f acc[2][4];
+        zero_acc(acc);
+        wave_gemm<2, 4, 4>(L.DOT, 64, L.H2T, 64, acc);
+        for (int mi = 0; mi < 2; ++mi)
+            for (int ni = 0; ni < 4; ++ni)
+                for (int e = 0; e < 4; ++e) {
+                    const int o = 16 * mi + rg + e, i = 16 * ni + col;
+                    if (o < 20) atomicAdd(&tv.grad[kPW3 + o * 64 + i], acc[mi][ni][e]);
+                }
+    }
+    // dH2[s][i] = sum_o dOut[s][o] W3[o][i]; dA2 = dH2 * silu'(A2), stored
+    // over H2 (row-major) and H2T (transposed)
+    {
+        v4f acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4, 4, 2>(L.DO, 32, L.w.w3t, 32, acc);
+        __syncthreads();
+        for (int ni = 0; ni < 4; ++ni) {
+            float cs = 0.0f;
+            for (int mi = 0; mi < 4; ++mi)
+                for (int e = 0; e < 4; ++e) {
+                    const int s = 16 * mi + rg + e, i = 16 * ni + col;
+                    const float dA = acc[mi][ni][e] * dsilu(L.A2[s * 64 + i]);
+                    cs += dA;
+                    const uint16_t b = f2bf(dA);
+                    L.H2[s * 64 + i] = b;
+                    L.H2T[i * 64 + s] = b;
+                }
+            cs += __shfl_xor(cs, 16, 64);
+            cs += __shfl_xor(cs, 32, 64);
+            if (lane < 16) atomicAdd(&tv.grad[kPB2 + 16 * ni + col], cs);
+        }
+    }
+    __syncthreads();
+    // dW2[o][i] = sum_s dA2[s][o] H1[s][i]
+    {
+        v4f acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4, 4, 4>(L.H2T, 64, L.H1T, 64, acc);
+        for (int mi = 0; mi < 4; ++mi)
+            for (int ni = 0; ni < 4; ++ni)
+                for (int e = 0; e < 4; ++e) {
+                    const int o = 16 * mi + rg + e, i = 16 * ni + col;
+                    atomicAdd(&tv.grad[kPW2 + o * 64 + i], acc[mi][ni][e]);
+                }
+    }
+    // dH1[s][i] = sum_o dA2[s][o] W2[o][i]; dA1 = dH1 * silu'(A1), stored
+    // transposed over H1T
+    {
+        v4f acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4, 4, 4>(L.H2, 64, L.w.w2t, 64, acc);
+        __syncthreads();
+        for (int ni = 0; ni < 4; ++ni) {
+            float cs = 0.0f;
+            for (int mi = 0; mi < 4; ++mi)
+                for (int e = 0; e < 4; ++e) {
+                    const int s = 16 * mi + rg + e, i = 16 * ni + col;
+                    const float dA = acc[mi][ni][e] * dsilu(L.A1[s * 64 + i]);
+                    cs += dA;
+                    L.H1T[i * 64 + s] = f2bf(dA);
+                }
+            cs += __shfl_xor(cs, 16, 64);
+            cs += __shfl_xor(cs, 32, 64);
+            if (lane < 16) atomicAdd(&tv.grad[kPB1 + 16 * ni + col], cs);
+        }
+    }
+    __syncthreads();
+    // dW1[o][i] = sum_s dA1[s][o] X[s][i]
+    {
+        v4f acc[4][2];
+        zero_acc(acc);
+        wave_gemm<4, 2, 4>(L.H1T, 64, L.XT, 64, acc);
+        for (int mi = 0; mi < 4; ++mi)
+            for (int ni = 0; ni < 2; ++ni)
+                for (int e = 0; e < 4; ++e) {
+                    const int o = 16 * mi + rg + e, i = 16 * ni + col;
+                    if (i < 24) atomicAdd(&tv.grad[kPW1 + o * 24 + i], acc[mi][ni][e]);
+                }
+    }
+}
+
+// Forward only, for given features (diagnostic): out[B][20].
+__global__ void __launch_bounds__(64) k_forward(const PackedW *W, const float *F, uint32_t B,
+                                                float *out) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LdsTrain &L = *reinterpret_cast<LdsTrain *>(lds_raw);
+    const int lane = threadIdx.x;
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(W);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.w);
+        for (uint32_t k = lane; k < sizeof(PackedW) / 4; k += 64) dst[k] = src[k];
+    }
+    const uint32_t s = blockIdx.x * 64 + lane;
+    for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = (s < B && k < 24) ? f2bf(F[(size_t)s * 24 + k]) : 0;
+    __syncthreads();
+    FwdBufs fb{L.X, L.H1, L.H2, nullptr, nullptr, nullptr, nullptr, nullptr, L.OUT};
+    mlp_forward_wave(L.w, fb);
+    if (s < B)
+        for (int k = 0; k < 20; ++k) out[(size_t)s * 20 + k] = L.OUT[32 * lane + k];
+}
+
+// Adam on the fp32 master vector; rewrites the packed bf16 weights and
+// clears the gradient.
+__global__ void k_adam(float *p, float *m, float *vv, float *grad, PackedW *W, uint32_t step,
+                       float lr, int update) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint32_t)kNPARAM) return;
+    float x = p[e];
+    if (update) {
+        const float g = grad[e];
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float mm = b1 * m[e] + (1.0f - b1) * g;
+        const float v2 = b2 * vv[e] + (1.0f - b2) * g * g;
+        m[e] = mm;
+        vv[e] = v2;
+        const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+        x -= lr * (mm / c1) / (sqrtf(v2 / c2) + 1e-8f);
+        p[e] = x;
+    }
+    grad[e] = 0.0f;
+    const uint16_t b = f2bf(x);
+    if (e < (uint32_t)kPB1) {
+        const uint32_t o = e / 24, i = e % 24;
+        W->w1[o * 32 + i] = b;
+    } else if (e < (uint32_t)kPW2) {
+        W->b1[e - kPB1] = x;
+    } else if (e < (uint32_t)kPB2) {
+        const uint32_t o = (e - kPW2) / 64, i = (e - kPW2) % 64;
+        W->w2[o * 64 + i] = b;
+        W->w2t[i * 64 + o] = b;
+    } else if (e < (uint32_t)kPW3) {
+        W->b2[e - kPB2] = x;
+    } else if (e < (uint32_t)kPB3) {
+        const uint32_t o = (e - kPW3) / 64, i = (e - kPW3) % 64;
+        W->w3[o * 64 + i] = b;
+        W->w3t[i * 32 + o] = b;
+    } else {
+        W->b3[e - kPB3] = x;
+    }
+}
+
+}  // namespace mpmc
+
+// ===========================================================================
+// host side
+using namespace mpmc;
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MPMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+namespace {
+struct Learner {
+    hipStream_t stream = nullptr;
+    uint64_t seed = 0;
+    float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    PackedW *W = nullptr;
+    double *loss = nullptr;
+    float *F = nullptr, *D = nullptr;
+    unsigned long long *count = nullptr, *over = nullptr;
+    uint64_t cap = 0;
+    uint32_t step = 0;
+    std::vector<void *> allocs;
+
+    int alloc(void **q, size_t n) {
+        hipError_t e = hipMalloc(q, n ? n : 4);
+        if (e != hipSuccess) return fail(MPMC_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+        allocs.push_back(*q);
+        return MPMC_OK;
+    }
+    void release() {
+        for (void *q : allocs) (void)hipFree(q);
+        allocs.clear();
+    }
+    // re-pack bf16 weights from the master vector without an update
+    int pack() {
+        k_adam<<<(kNPARAM + 255) / 256, 256, 0, stream>>>(p, m, v, grad, W, 1, 0.0f, 0);
+        HIPCHK(hipGetLastError());
+        return MPMC_OK;
+    }
+};
+Learner *LR(mpmc_learner l) { return reinterpret_cast<Learner *>(l); }
+Box *BX(mpmc_box b) { return reinterpret_cast<Box *>(b); }
+
+// Default initialisation: weights uniform in +-1/sqrt(fan_in) from Philox
+// words, biases zero except the log widths of the mixture, log(0.05).
+void default_params(uint64_t seed, std::vector<float> &P) {
+    P.assign(kNPARAM, 0.0f);
+    auto uni = [&](uint32_t i) {
+        const Words w = philox((uint32_t)seed, (uint32_t)(seed >> 32), i, 0, 0, 6);
+        return ((float)(w.w0 >> 8) + 0.5f) * (1.0f / 16777216.0f) * 2.0f - 1.0f;
+    };
+    for (int e = kPW1; e < kPB1; ++e) P[e] = uni(e) / sqrtf(24.0f);
+    for (int e = kPW2; e < kPB2; ++e) P[e] = uni(e) / sqrtf(64.0f);
+    for (int e = kPW3; e < kPB3; ++e) P[e] = 0.1f * uni(e) / sqrtf(64.0f);
+    for (int k = 0; k < 4; ++k) {
+        P[kPB3 + 5 * k + 3] = logf(0.05f);
+        P[kPB3 + 5 * k + 4] = logf(0.05f);
+    }
+}
+}  // namespace
+
+extern "C" int mpmc_learner_create(mpmc_learner *out, uint64_t seed, uint64_t capacity,
+                                   void *stream) {
+    if (!out) return fail(MPMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    Learner *l = new Learner();
+    l->stream = (hipStream_t)stream;
+    l->seed = seed;
+    l->cap = capacity;
+    int rc = MPMC_OK;
+    for (float **q : {&l->p, &l->m, &l->v, &l->grad})
+        if (!rc) rc = l->alloc((void **)q, kNPARAM * 4);
+    if (!rc) rc = l->alloc((void **)&l->W, sizeof(PackedW));
+    if (!rc) rc = l->alloc((void **)&l->loss, 8);
+    if (!rc) rc = l->alloc((void **)&l->count, 16);
+    if (!rc) rc = l->alloc((void **)&l->F, capacity * 24 * 4);
+    if (!rc) rc = l->alloc((void **)&l->D, capacity * 2 * 4);
+    if (rc) {
+        l->release();
+        delete l;
+        return rc;
+    }
+    l->over = l->count + 1;
+    std::vector<float> P;
+    default_params(seed, P);
+    hipError_t e = hipMemsetAsync(l->W, 0, sizeof(PackedW), l->stream);
+    for (float *q : {l->m, l->v, l->grad})
+        if (e == hipSuccess) e = hipMemsetAsync(q, 0, kNPARAM * 4, l->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(l->count, 0, 16, l->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(l->p, P.data(), kNPARAM * 4, hipMemcpyHostToDevice, l->stream);
+    if (e != hipSuccess) {
+        l->release();
+        delete l;
+        return fail(MPMC_EDEVICE, "learner set-up: %s", hipGetErrorString(e));
+    }
+    rc = l->pack();
+    if (rc == MPMC_OK && hipStreamSynchronize(l->stream) != hipSuccess) rc = fail(MPMC_EDEVICE, "sync");
+    if (rc) {
+        l->release();
+        delete l;
+        return rc;
+    }
+    *out = reinterpret_cast<mpmc_learner>(l);
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_free(mpmc_learner lh) {
+    if (!lh) return MPMC_OK;
+    (void)hipStreamSynchronize(LR(lh)->stream);
+    LR(lh)->release();
+    delete LR(lh);
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_set_params(mpmc_learner lh, const float *params) {
+    if (!lh || !params) return fail(MPMC_EINVAL, "NULL argument");
+    Learner *l = LR(lh);
+    HIPCHK(hipMemcpyAsync(l->p, params, kNPARAM * 4, hipMemcpyHostToDevice, l->stream));
+    HIPCHK(hipMemsetAsync(l->m, 0, kNPARAM * 4, l->stream));
+    HIPCHK(hipMemsetAsync(l->v, 0, kNPARAM * 4, l->stream));
+    l->step = 0;
+    int rc = l->pack();
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(l->stream));
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_get_params(mpmc_learner lh, float *params) {
+    if (!lh || !params) return fail(MPMC_EINVAL, "NULL argument");
+    Learner *l = LR(lh);
+    HIPCHK(hipMemcpyAsync(params, l->p, kNPARAM * 4, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipStreamSynchronize(l->stream));
+    return MPMC_OK;
+}
+
+static int check_learned_box(Box *b) {
+    if ((double)b->g.w < 3.0)
+        return fail(MPMC_EINVAL, "the learned proposal needs cells of width >= 3 sigma "
+                                 "(create the box with cell_min = 3)");
+    if (!b->placed) return fail(MPMC_ESTATE, "no configuration");
+    if (b->in_batch) return fail(MPMC_ESTATE, "batch members are swept by the batch");
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_collect(mpmc_learner lh, mpmc_box bh, uint64_t sweeps, uint64_t *n_total) {
+    if (!lh || !bh) return fail(MPMC_EINVAL, "NULL argument");
+    Learner *l = LR(lh);
+    Box *b = BX(bh);
+    int rc = check_learned_box(b);
+    if (rc) return rc;
+    CollectView cv{l->F, l->D, l->count, l->cap};
+    const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
+    for (uint64_t s = 0; s < sweeps; ++s) {
+        BoxView v = b->view(b->cur);
+        launch_simple_sweep_rebin_only(v, b->stream);
+        for (uint32_t p = 0; p < 4; ++p) k_pass_collect<<<(na + 127) / 128, 128, 0, b->stream>>>(v, p, cv);
+        launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
+                       1, b->stream);
+        HIPCHK(hipGetLastError());
+        b->cur ^= 1;
+    }
+    if (n_total) {
+        unsigned long long c = 0;
+        HIPCHK(hipMemcpyAsync(&c, l->count, 8, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        *n_total = c < l->cap ? c : l->cap;
+    }
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_train(mpmc_learner lh, uint32_t steps, uint32_t batch, float lr,
+                                  double *mean_loss) {
+    if (!lh || batch == 0) return fail(MPMC_EINVAL, "bad arguments");
+    Learner *l = LR(lh);
+    unsigned long long n = 0;
+    HIPCHK(hipMemcpyAsync(&n, l->count, 8, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipStreamSynchronize(l->stream));
+    if (n > l->cap) n = l->cap;
+    if (n == 0) return fail(MPMC_ESTATE, "the data set is empty: collect moves first");
+    const size_t lds = sizeof(LdsTrain);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+    }
+    double last = 0.0;
+    for (uint32_t s = 0; s < steps; ++s) {
+        ++l->step;
+        TrainView tv{l->W, l->F, l->D, n, nullptr, batch, (uint32_t)l->seed, (uint32_t)(l->seed >> 32),
+                     l->step, l->grad, l->loss};
+        HIPCHK(hipMemsetAsync(l->loss, 0, 8, l->stream));
+        k_train<<<(batch + 63) / 64, 64, lds, l->stream>>>(tv);
+        k_adam<<<(kNPARAM + 255) / 256, 256, 0, l->stream>>>(l->p, l->m, l->v, l->grad, l->W, l->step, lr, 1);
+        HIPCHK(hipGetLastError());
+        if (s + 1 == steps) {
+            HIPCHK(hipMemcpyAsync(&last, l->loss, 8, hipMemcpyDeviceToHost, l->stream));
+            HIPCHK(hipStreamSynchronize(l->stream));
+        }
+    }
+    if (mean_loss) *mean_loss = last / batch;
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_forward(mpmc_learner lh, const float *F, uint32_t B, float *out) {
+    if (!lh || !F || !out || B == 0) return fail(MPMC_EINVAL, "bad arguments");
+    Learner *l = LR(lh);
+    float *dF = nullptr, *dO = nullptr;
+    HIPCHK(hipMalloc((void **)&dF, (size_t)B * 24 * 4));
+    hipError_t e = hipMalloc((void **)&dO, (size_t)B * 20 * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(dF, F, (size_t)B * 24 * 4, hipMemcpyHostToDevice, l->stream);
+    const size_t lds = sizeof(LdsTrain);
+    if (e == hipSuccess) {
+        e = hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_forward<<<(B + 63) / 64, 64, lds, l->stream>>>(l->W, dF, B, dO);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dO, (size_t)B * 20 * 4, hipMemcpyDeviceToHost, l->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(l->stream);
+    (void)hipFree(dF);
+    if (dO) (void)hipFree(dO);
+    if (e != hipSuccess) return fail(MPMC_EDEVICE, "forward: %s", hipGetErrorString(e));
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_nll_grad(mpmc_learner lh, const float *F, const float *D, uint32_t B,
+                                     float *grad, double *loss) {
+    if (!lh || !F || !D || !grad || B == 0) return fail(MPMC_EINVAL, "bad arguments");
+    Learner *l = LR(lh);
+    float *dF = nullptr, *dD = nullptr;
+    uint32_t *idx = nullptr;
+    HIPCHK(hipMalloc((void **)&dF, (size_t)B * 24 * 4));
+    hipError_t e = hipMalloc((void **)&dD, (size_t)B * 2 * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&idx, (size_t)B * 4);
+    std::vector<uint32_t> hi(B);
+    for (uint32_t i = 0; i < B; ++i) hi[i] = i;
+    if (e == hipSuccess) e = hipMemcpyAsync(dF, F, (size_t)B * 24 * 4, hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dD, D, (size_t)B * 2 * 4, hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(idx, hi.data(), (size_t)B * 4, hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(l->grad, 0, kNPARAM * 4, l->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(l->loss, 0, 8, l->stream);
+    const size_t lds = sizeof(LdsTrain);
+    if (e == hipSuccess) {
+        e = hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        TrainView tv{l->W, dF, dD, B, idx, B, 0, 0, 0, l->grad, l->loss};
+        k_train<<<(B + 63) / 64, 64, lds, l->stream>>>(tv);
+        e = hipGetLastError();
+    }
+    double sum = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, l->grad, kNPARAM * 4, hipMemcpyDeviceToHost, l->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&sum, l->loss, 8, hipMemcpyDeviceToHost, l->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(l->grad, 0, kNPARAM * 4, l->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(l->stream);
+    (void)hipFree(dF);
+    if (dD) (void)hipFree(dD);
+    if (idx) (void)hipFree(idx);
+    if (e != hipSuccess) return fail(MPMC_EDEVICE, "nll_grad: %s", hipGetErrorString(e));
+    if (loss) *loss = sum / B;
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learned_features(mpmc_box bh, const uint32_t *tags, uint32_t n, float *F) {
+    if (!bh || !tags || !F || n == 0) return fail(MPMC_EINVAL, "bad arguments");
+    Box *b = BX(bh);
+    if ((double)b->g.w < 3.0) return fail(MPMC_EINVAL, "features need cells of width >= 3 sigma");
+    std::vector<int32_t> row(b->N, -1);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (tags[i] >= b->N) return fail(MPMC_EINVAL, "tag %u out of range", tags[i]);
+        row[tags[i]] = (int32_t)i;
+    }
+    int32_t *drow = nullptr;
+    float *dF = nullptr;
+    HIPCHK(hipMalloc((void **)&drow, (size_t)b->N * 4));
+    hipError_t e = hipMalloc((void **)&dF, (size_t)n * 24 * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(drow, row.data(), (size_t)b->N * 4, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(dF, 0, (size_t)n * 24 * 4, b->stream);
+    if (e == hipSuccess) {
+        const uint32_t tot = b->g.M * b->g.M * b->g.CS;
+        k_features<<<(tot + 255) / 256, 256, 0, b->stream>>>(b->cnt[b->cur], b->x[b->cur], b->y[b->cur],
+                                                             b->tag[b->cur], b->g.M, b->g.CS, b->g.w, drow, dF);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(F, dF, (size_t)n * 24 * 4, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(drow);
+    if (dF) (void)hipFree(dF);
+    if (e != hipSuccess) return fail(MPMC_EDEVICE, "features: %s", hipGetErrorString(e));
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, float eps,
+                                  uint64_t *trials, uint64_t *accepts) {
+    if (!bh || !lh) return fail(MPMC_EINVAL, "NULL argument");
+    if (!(eps >= 0.0f) || eps > 1.0f) return fail(MPMC_EINVAL, "eps must be in [0, 1]");
+    Box *b = BX(bh);
+    Learner *l = LR(lh);
+    int rc = check_learned_box(b);
+    if (rc) return rc;
+    rc = b->read_scalars();
+    if (rc) return rc;
+    const DevScalars before = b->host;
+    const size_t lds = sizeof(LdsLearn);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_pass_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        attr = true;
+    }
+    LearnView lv{l->W, eps, l->over};
+    const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
+    for (uint64_t s = 0; s < k; ++s) {
+        BoxView v = b->view(b->cur);
+        launch_simple_sweep_rebin_only(v, b->stream);
+        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + 63) / 64, 64, lds, b->stream>>>(v, p, lv);
+        launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
+                       1, b->stream);
+        HIPCHK(hipGetLastError());
+        b->cur ^= 1;
+    }
+    if (trials || accepts) {
+        rc = b->read_scalars();
+        if (rc) return rc;
+        if (trials) *trials = b->host.trials - before.trials;
+        if (accepts) *accepts = b->host.accepts - before.accepts;
+    }
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_info(mpmc_learner lh, uint64_t *n_data, uint64_t *n_feature_overflow,
+                                 uint32_t *steps) {
+    if (!lh) return fail(MPMC_EINVAL, "NULL learner");
+    Learner *l = LR(lh);
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, l->count, 16, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipStreamSynchronize(l->stream));
+    if (n_data) *n_data = c[0] < l->cap ? c[0] : l->cap;
+    if (n_feature_overflow) *n_feature_overflow = c[1];
+    if (steps) *steps = l->step;
+    return MPMC_OK;
+}

@@ -31,6 +31,7 @@ __device__ __forceinline__ void count_trials(DevScalars *dev, uint32_t t, uint32
 
 // sweep_simple.hip
 void launch_simple_sweep(const BoxView &v, hipStream_t st);
+void launch_simple_sweep_rebin_only(const BoxView &v, hipStream_t st);
 void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,
                     long long Lq, uint32_t count, hipStream_t st);
 

@@ -156,6 +156,11 @@ void launch_simple_sweep(const BoxView &v, hipStream_t st) {
     for (uint32_t p = 0; p < 4; ++p) k_pass<<<(na + 255) / 256, 256, 0, st>>>(v, p);
 }
 
+void launch_simple_sweep_rebin_only(const BoxView &v, hipStream_t st) {
+    const uint32_t nc = v.M * v.M;
+    k_rebin<<<(nc + 255) / 256, 256, 0, st>>>(v);
+}
+
 void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,
                     long long Lq, uint32_t count, hipStream_t st) {
     k_advance<<<1, 64, 0, st>>>(dev, seed_lo, seed_hi, W, Lq, count);

@@ -85,6 +85,18 @@ _SIGS = {
     "mpmc_batch_info": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                         C.POINTER(C.c_uint32)],
     "mpmc_batch_set_graphs": [_P, C.c_uint32],
+    "mpmc_learner_create": [C.POINTER(C.c_void_p), C.c_uint64, C.c_uint64, _P],
+    "mpmc_learner_free": [_P],
+    "mpmc_learner_set_params": [_P, _P],
+    "mpmc_learner_get_params": [_P, _P],
+    "mpmc_learner_collect": [_P, _P, C.c_uint64, C.POINTER(C.c_uint64)],
+    "mpmc_learner_train": [_P, C.c_uint32, C.c_uint32, C.c_float, C.POINTER(C.c_double)],
+    "mpmc_learner_forward": [_P, _P, C.c_uint32, _P],
+    "mpmc_learner_nll_grad": [_P, _P, _P, C.c_uint32, _P, C.POINTER(C.c_double)],
+    "mpmc_learner_info": [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)],
+    "mpmc_learned_features": [_P, _P, C.c_uint32, _P],
+    "mpmc_sweep_learned": [_P, _P, C.c_uint64, C.c_float, C.POINTER(C.c_uint64),
+                           C.POINTER(C.c_uint64)],
 }
 
 
@@ -386,6 +398,81 @@ class Batch:
         n, t, th, it = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
         _check(_lib.mpmc_batch_info(self.h, C.byref(n), C.byref(t), C.byref(th), C.byref(it)))
         return dict(nbox=n.value, tile=t.value, threads=th.value, n_items=it.value)
+
+
+MLP_PARAMS = 7060
+
+
+class Learner:
+    """The learned proposal: network parameters, recorded moves, training."""
+
+    def __init__(self, seed=0, capacity=1 << 20, stream=None):
+        lib = load()
+        h = C.c_void_p()
+        st = stream if stream is not None else _current_stream()
+        _check(lib.mpmc_learner_create(C.byref(h), seed, capacity, st))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.mpmc_learner_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self):
+        p = np.zeros(MLP_PARAMS, np.float32)
+        _check(_lib.mpmc_learner_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == MLP_PARAMS
+        _check(_lib.mpmc_learner_set_params(self.h, _ptr(p)))
+
+    def collect(self, box, sweeps):
+        n = C.c_uint64()
+        _check(_lib.mpmc_learner_collect(self.h, box.h, sweeps, C.byref(n)))
+        return n.value
+
+    def train(self, steps, batch=4096, lr=1e-3):
+        loss = C.c_double()
+        _check(_lib.mpmc_learner_train(self.h, steps, batch, lr, C.byref(loss)))
+        return loss.value
+
+    def forward(self, F):
+        F = np.ascontiguousarray(F, np.float32)
+        out = np.zeros((F.shape[0], 20), np.float32)
+        _check(_lib.mpmc_learner_forward(self.h, _ptr(F), F.shape[0], _ptr(out)))
+        return out
+
+    def nll_grad(self, F, D):
+        F = np.ascontiguousarray(F, np.float32)
+        D = np.ascontiguousarray(D, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        loss = C.c_double()
+        _check(_lib.mpmc_learner_nll_grad(self.h, _ptr(F), _ptr(D), F.shape[0], _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def info(self):
+        n, o, s = C.c_uint64(), C.c_uint64(), C.c_uint32()
+        _check(_lib.mpmc_learner_info(self.h, C.byref(n), C.byref(o), C.byref(s)))
+        return dict(n_data=n.value, feature_overflow=o.value, steps=s.value)
+
+
+def learned_features(box, tags):
+    tags = np.ascontiguousarray(tags, np.uint32)
+    F = np.zeros((len(tags), 24), np.float32)
+    _check(load().mpmc_learned_features(box.h, _ptr(tags), len(tags), _ptr(F)))
+    return F
+
+
+def sweep_learned(box, learner, k=1, eps=0.1, counts=False):
+    t, a = C.c_uint64(), C.c_uint64()
+    _check(load().mpmc_sweep_learned(box.h, learner.h, k, eps, C.byref(t) if counts else None,
+                                     C.byref(a) if counts else None))
+    return (t.value, a.value) if counts else None
 
 
 def acf(series, maxlag):
