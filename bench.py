@@ -50,6 +50,94 @@ def tune_step(box, target=0.30, rounds=6, block=100):
     return m, acc
 
 
+def kernel_source_digest():
+    """Digest of the sources of the timed sweep kernel, to tell whether a
+    stored counter profile still describes it."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep_fused.hip", "mpmc_common.hpp", "mpmc_kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1211_1645_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    if it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_fused_1024sq_eta0716.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_digest") != kernel_source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def copy_calibration(nbytes=512 << 20, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
+
+
+def learned_comparison(seed, minutes_budget=0.5):
+    """Learned proposal against the uniform one on the same w >= 3 cell grid
+    at N = 1024^2, eta = 0.716: train on accepted moves of an N = 256^2 box,
+    then measure acceptance, mean squared displacement per trial and per
+    second."""
+    import numpy as np
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    Q = 2.0 ** -22
+    tb = mp.Box(65536, ETA, seed=seed + 1, step_m=40, cell_min=3.0, schedule="simple")
+    m_train, _ = tune_step(tb)
+    tb.sweep(200)
+    L = mp.Learner(seed=seed + 2, capacity=1 << 22)
+    n = L.collect(tb, 150)
+    t0 = time.perf_counter()
+    loss0 = L.train(1, batch=8192, lr=2e-3)
+    loss = L.train(3000, batch=8192, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"train": {"moves": n, "steps": 3001, "batch": 8192, "loss_first": loss0,
+                     "loss_last": loss, "seconds": train_s}}
+    for mode in ("uniform", "learned"):
+        b = mp.Box(N_DISKS, ETA, seed=seed + 3, step_m=40, cell_min=3.0, schedule="simple")
+        m, _ = tune_step(b)
+        b.sweep(50)
+        run = (lambda k: b.sweep(k)) if mode == "uniform" else \
+            (lambda k: mp.sweep_learned(b, L, k, eps=0.1))
+        run(2)
+        X0, Y0 = b.positions_q()
+        i0 = b.info()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run(20)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        X1, Y1 = b.positions_q()
+        i1 = b.info()
+        Lq = i1["W"] * i1["M"]
+        dx = (X1 - X0) % Lq
+        dx = np.where(2 * dx > Lq, dx - Lq, dx) * Q
+        dy = (Y1 - Y0) % Lq
+        dy = np.where(2 * dy > Lq, dy - Lq, dy) * Q
+        tr = i1["trials"] - i0["trials"]
+        msd = float(np.mean(dx * dx + dy * dy))
+        out[mode] = {"step_m": m, "acceptance": (i1["accepts"] - i0["accepts"]) / tr,
+                     "trial_moves_per_s": tr / dt, "sweep_us": dt / 20 * 1e6,
+                     "msd_per_trial_per_disk": msd * b.N / tr, "msd_per_s": msd / dt}
+    out["gain_msd_per_trial"] = out["learned"]["msd_per_trial_per_disk"] / \
+        out["uniform"]["msd_per_trial_per_disk"]
+    out["gain_msd_per_s"] = out["learned"]["msd_per_s"] / out["uniform"]["msd_per_s"]
+    return out
+
+
 def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
     """The oracle (single thread) on the same start and step: sweeps of the
     full 1024^2 box until about target_seconds of CPU work."""
@@ -79,6 +167,9 @@ def main():
     ap.add_argument("--sweeps", type=int, default=100, help="sweeps per benchmark step")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sampler runs one box per GPU and this build "
@@ -89,6 +180,9 @@ def main():
     import paper_1211_1645_amd.mpmc as mp
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular",
@@ -158,10 +252,13 @@ def main():
         "abs_Psi6_mean": sum(abs(p) for p in psi_series) / len(psi_series),
         "validate": {"overlaps": overlaps, "bad": bad},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
                      "kernel": "k_fused (one sweep per launch)",
-                     "algorithmic_bytes_per_launch": bytes_per},
+                     "algorithmic_bytes_per_launch": bytes_per,
+                     "kernel_digest": kernel_source_digest()},
     }
+    if not args.no_learned:
+        line["learned_vs_uniform"] = learned_comparison(args.seed)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(0, args.seed, step_m)
     print(json.dumps(line))

@@ -4,6 +4,7 @@
 // The trajectory is independent of the choice (counter-keyed random numbers
 // and independent same-colour cells), so tuning can never change results.
 #include <map>
+#include <vector>
 #include <mutex>
 #include <tuple>
 
@@ -55,13 +56,19 @@ static int autotune(Box *b, FusedShape *best) {
     float best_ms = 1e30f;
     bool found = false;
     const BoxView v = b->view(b->cur);
-    for (uint32_t i = 0; i < n; ++i) {
-        if (!fused_supported(v, shapes[i])) continue;
-        float ms;
-        rc = time_shape(b, shapes[i], 10, &ms);
-        if (rc) return rc;
-        if (ms < best_ms) { best_ms = ms; *best = shapes[i]; found = true; }
-    }
+    // three interleaved rounds, best time per shape, so that one noisy
+    // measurement does not decide
+    std::vector<float> t(n, 1e30f);
+    for (int round = 0; round < 3; ++round)
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!fused_supported(v, shapes[i])) continue;
+            float ms;
+            rc = time_shape(b, shapes[i], 10, &ms);
+            if (rc) return rc;
+            t[i] = ms < t[i] ? ms : t[i];
+        }
+    for (uint32_t i = 0; i < n; ++i)
+        if (t[i] < best_ms) { best_ms = t[i]; *best = shapes[i]; found = true; }
     // restore the counters the timing launches advanced
     if (hipMemcpyAsync(b->dev, &saved, sizeof(DevScalars), hipMemcpyHostToDevice, b->stream) !=
             hipSuccess ||

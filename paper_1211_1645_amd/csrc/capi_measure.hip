@@ -63,6 +63,16 @@ int mpmc::lsq_poly(const std::vector<double> &t, const std::vector<double> &yv, 
     return 0;
 }
 
+int Box::locate() {
+    if (!loc) {
+        int rc = alloc_dev((void **)&loc, (size_t)N * 4);
+        if (rc) return rc;
+    }
+    launch_locate(mview(), loc, stream);
+    HIPCHK(hipGetLastError());
+    return MPMC_OK;
+}
+
 // P* from ordered pair counts of n_conf configurations.
 static int pressure_from_counts(const Box *b, const unsigned long long *ordered, uint64_t n_conf,
                                 double *P, double *g0, double *Z) {
@@ -94,7 +104,9 @@ extern "C" int mpmc_accumulate_contacts(mpmc_box bh) {
     const uint32_t K = b->p.hist_bins;
     const double rmax = 2.0 + K * b->p.hist_dr;
     const uint32_t h = ((double)b->g.w >= rmax) ? 1u : 2u;
-    launch_contact_hist(b->mview(), b->edges, K, h, b->hist, nullptr, b->stream);
+    int lrc = b->locate();
+    if (lrc) return lrc;
+    launch_contact_hist(b->mview(), b->edges, K, h, b->hist, nullptr, b->loc, b->stream);
     HIPCHK(hipGetLastError());
     ++b->n_conf;
     if (b->p.hist_block > 0 && b->n_conf - b->block_conf0 == b->p.hist_block) {
@@ -175,8 +187,10 @@ extern "C" int mpmc_contact_hist_subset(mpmc_box bh, const uint8_t *sel, int64_t
     HIPCHK(hipMemcpyAsync(dsel, sel, b->N, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemsetAsync(dh, 0, K * 8, b->stream));
     const double rmax = 2.0 + K * b->p.hist_dr;
+    rc = b->locate();
+    if (rc) return rc;
     launch_contact_hist(b->mview(), b->edges, K, ((double)b->g.w >= rmax) ? 1u : 2u, dh, dsel,
-                        b->stream);
+                        b->loc, b->stream);
     HIPCHK(hipGetLastError());
     std::vector<unsigned long long> h(K);
     HIPCHK(hipMemcpyAsync(h.data(), dh, K * 8, hipMemcpyDeviceToHost, b->stream));
@@ -213,10 +227,12 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
     const uint32_t hmax = (M - 2) / 2;  // 2h + 1 <= M - 1: no cell seen twice
     uint32_t h = hmax < 2 ? hmax : 2;
     if (h < 1) return fail(MPMC_EINVAL, "box too small for the neighbour search");
+    rc = b->locate();
+    if (rc) return rc;
     for (;;) {
         HIPCHK(hipMemsetAsync(&b->dev->psi_re, 0, 16, b->stream));
         HIPCHK(hipMemsetAsync(b->scratch_u32, 0, 4, b->stream));
-        launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->stream);
+        launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->loc, b->stream);
         HIPCHK(hipGetLastError());
         uint32_t failed = 0;
         HIPCHK(hipMemcpyAsync(&failed, b->scratch_u32, 4, hipMemcpyDeviceToHost, b->stream));

@@ -21,39 +21,45 @@ __device__ __forceinline__ uint32_t wrapc(int v, uint32_t M) {
 __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float *__restrict__ E,
                                                       uint32_t K, int h,
                                                       unsigned long long *hist,
-                                                      const uint8_t *sel) {
+                                                      const uint8_t *sel, const uint32_t *loc) {
     extern __shared__ uint32_t bins[];
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
     __syncthreads();
     const uint32_t M = m.M;
-    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell < M * M) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m.N && (!sel || sel[t])) {
+        const uint32_t cell = loc[t] / m.CS, s = loc[t] % m.CS;
         const uint32_t ci = cell % M, cj = cell / M;
-        const uint32_t n = m.cnt[cell];
         const float e0 = E[0], eK = E[K];
-        for (uint32_t s = 0; s < n; ++s) {
-            if (sel && !sel[m.tag[cell * m.CS + s]]) continue;
-            const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
-            for (int dj = -h; dj <= h; ++dj)
-                for (int di = -h; di <= h; ++di) {
-                    const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
-                    const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
-                    const uint32_t mm = m.cnt[nb];
-                    for (uint32_t t = 0; t < mm; ++t) {
-                        if (di == 0 && dj == 0 && t == s) continue;
-                        const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
-                        const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
-                        const float r2 = r2_f32(dx, dy);
-                        if (!(r2 >= e0) || !(r2 < eK)) continue;
-                        // start from the square-root estimate, then settle
-                        // on the exact fp32 edges
-                        int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
-                        k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
-                        while (k > 0 && r2 < E[k]) --k;
-                        while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
-                        atomicAdd(&bins[k], 1u);
-                    }
+        const float rmax = sqrtf(eK) * 1.0001f + 1e-4f;  // conservative reach
+        const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
+        for (int dj = -h; dj <= h; ++dj) {
+            // smallest |dy| to any disk of row dj: skip rows out of reach
+            const float gy = dj > 1 ? (float)(dj - 1) * m.w + (m.w - yi)
+                           : dj < -1 ? (float)(-dj - 1) * m.w + yi : 0.0f;
+            if (gy > rmax) continue;
+            for (int di = -h; di <= h; ++di) {
+                const float gx = di > 1 ? (float)(di - 1) * m.w + (m.w - xi)
+                               : di < -1 ? (float)(-di - 1) * m.w + xi : 0.0f;
+                if (gx > rmax) continue;
+                const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+                const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                const uint32_t mm = m.cnt[nb];
+                for (uint32_t q = 0; q < mm; ++q) {
+                    if (di == 0 && dj == 0 && q == s) continue;
+                    const float dx = (m.x[nb * m.CS + q] - xi) + cwx;
+                    const float dy = (m.y[nb * m.CS + q] - yi) + cwy;
+                    const float r2 = r2_f32(dx, dy);
+                    if (!(r2 >= e0) || !(r2 < eK)) continue;
+                    // start from the square-root estimate, then settle on the
+                    // exact fp32 edges
+                    int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
+                    k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
+                    while (k > 0 && r2 < E[k]) --k;
+                    while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
+                    atomicAdd(&bins[k], 1u);
                 }
+            }
         }
     }
     __syncthreads();
@@ -61,10 +67,25 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
         if (bins[k]) atomicAdd(&hist[k], (unsigned long long)bins[k]);
 }
 
+// Slot of every disk by tag: loc[tag] = cell * CS + slot.
+__global__ void __launch_bounds__(256) k_locate(MeasureView m, uint32_t *loc) {
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t cell = gid / m.CS, s = gid % m.CS;
+    if (cell >= m.M * m.M || s >= m.cnt[cell]) return;
+    const uint32_t tg = m.tag[cell * m.CS + s];
+    if (tg < m.N) loc[tg] = gid;
+}
+
+void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st) {
+    const uint32_t n = m.M * m.M * m.CS;
+    k_locate<<<(n + 255) / 256, 256, 0, st>>>(m, loc);
+}
+
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
-                         unsigned long long *hist, const uint8_t *sel, hipStream_t st) {
-    const uint32_t nc = m.M * m.M;
-    k_contact_hist<<<(nc + 255) / 256, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, hist, sel);
+                         unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
+                         hipStream_t st) {
+    k_contact_hist<<<(m.N + 255) / 256, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, hist,
+                                                                          sel, loc);
 }
 
 // ---------------------------------------------------------------------------
@@ -83,12 +104,12 @@ __device__ __forceinline__ bool nb_less(float ra, uint32_t ta, float rb, uint32_
 }
 
 __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, float *im,
-                                              uint32_t *fail) {
+                                              uint32_t *fail, const uint32_t *loc) {
     const uint32_t M = m.M;
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cell = gid / m.CS, s = gid % m.CS;
+    const uint32_t cell = gid < m.N ? loc[gid] / m.CS : 0, s = gid < m.N ? loc[gid] % m.CS : 0;
     double pr = 0.0, pi = 0.0;
-    if (cell < M * M && s < m.cnt[cell]) {
+    if (gid < m.N) {
         const uint32_t ci = cell % M, cj = cell / M;
         const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
         const uint32_t ti = m.tag[cell * m.CS + s];
@@ -151,9 +172,8 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
 }
 
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 hipStream_t st) {
-    const uint32_t n = m.M * m.M * m.CS;
-    k_psi6<<<(n + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail);
+                 const uint32_t *loc, hipStream_t st) {
+    k_psi6<<<(m.N + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail, loc);
 }
 
 // Coarse field: per cell, the mean psi_j over the disks of its 3 x 3 block.

@@ -48,6 +48,8 @@ struct Box {
     uint32_t *scratch_u32 = nullptr;
     void *pos_scratch[2] = {nullptr, nullptr};
     float *psi_buf = nullptr;  // re[N], im[N], field re/im[M*M]
+    uint32_t *loc = nullptr;   // slot of every disk by tag (measurement kernels)
+    int locate();              // fills loc for the current state
     uint64_t n_conf = 0;
     // blocks for the pressure standard error
     std::vector<unsigned long long> block_snapshot;

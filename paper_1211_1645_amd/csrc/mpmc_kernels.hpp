@@ -61,10 +61,13 @@ struct MeasureView {
     long long Sx, Sy, Lq;
 };
 // h: stencil half-width in cells (1 when w covers the histogram range)
+// Kernels over disks take loc[tag] = cell * CS + slot (launch_locate).
+void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st);
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
-                         unsigned long long *hist, const uint8_t *sel, hipStream_t st);
+                         unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
+                         hipStream_t st);
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 hipStream_t st);
+                 const uint32_t *loc, hipStream_t st);
 void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
                        float *fim, hipStream_t st);
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);

@@ -113,19 +113,28 @@ __global__ void __launch_bounds__(256) k_pass(BoxView v, uint32_t pass) {
 
 // Advances the device sweep counter by `count` and the accumulated shift by
 // the shifts of those sweeps.
+// One wave: lane l adds the shifts of sweeps l, l + 64, ...; the sums are
+// reduced across the wave and applied once (modulo the box side).
 __global__ void k_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,
                           long long Lq, uint32_t count) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    unsigned long long s = dev->sweep;
-    long long Sx = dev->Sx, Sy = dev->Sy;
-    for (uint32_t g = 0; g < count; ++g) {
+    if (blockIdx.x != 0) return;
+    const unsigned long long s = dev->sweep;
+    unsigned long long sx = 0, sy = 0;
+    for (uint32_t g = threadIdx.x; g < count; g += 64) {
         const SweepDraws d = sweep_draws(seed_lo, seed_hi, s + g, W);
-        Sx = (Sx + d.kx) % Lq;
-        Sy = (Sy + d.ky) % Lq;
+        sx += d.kx;
+        sy += d.ky;
     }
-    dev->Sx = Sx;
-    dev->Sy = Sy;
-    dev->sweep = s + count;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off, 64);
+        sy += __shfl_xor(sy, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        dev->Sx = (long long)(((unsigned long long)dev->Sx + sx) % (unsigned long long)Lq);
+        dev->Sy = (long long)(((unsigned long long)dev->Sy + sy) % (unsigned long long)Lq);
+        dev->sweep = s + count;
+    }
 }
 
 // The same for every box of a batch, one thread per box.
