@@ -18,13 +18,17 @@ std::map<std::tuple<int, uint32_t, uint32_t>, FusedShape> g_cache;  // (device, 
 }  // namespace
 
 // Times `reps` launches of one shape reading the current buffer and writing
-// the other one.  The current state and the sweep counter are untouched; the
-// trial counters are restored afterwards by the caller.
+// the other one, with no canonical output.  The canonical state (moved into
+// C by the caller first) and the sweep counter are untouched; the trial
+// counters are restored afterwards by the caller.
 static int time_shape(Box *b, const FusedShape &s, int reps, float *ms) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(MPMC_EDEVICE, "hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return fail(MPMC_EDEVICE, "hipEventCreate"); }
     BoxView v = b->view(b->cur);
+    v.cnt_can = nullptr;
+    v.x_can = v.y_can = nullptr;
+    v.tag_can = nullptr;
     for (int r = 0; r < 3; ++r) launch_fused_sweep(v, s, b->stream);
     hipEventRecord(e0, b->stream);
     for (int r = 0; r < reps; ++r) launch_fused_sweep(v, s, b->stream);
@@ -48,7 +52,9 @@ static int autotune(Box *b, FusedShape *best) {
         auto it = g_cache.find(key);
         if (it != g_cache.end()) { *best = it->second; return MPMC_OK; }
     }
-    int rc = b->read_scalars();
+    int rc = b->materialize();
+    if (rc) return rc;
+    rc = b->read_scalars();
     if (rc) return rc;
     const DevScalars saved = b->host;
     uint32_t n = 0;

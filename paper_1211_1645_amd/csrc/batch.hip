@@ -25,7 +25,9 @@ struct Batch {
     std::vector<Box *> boxes;
     mpmc_params p{};
     hipStream_t stream = nullptr, cap_stream = nullptr;
-    BoxView *d_views = nullptr;
+    BoxView *d_views = nullptr;    // per box and buffer parity
+    BoxView *d_views_t = nullptr;  // the same without canonical output, for timing
+    bool timing = false;
     uint32_t *d_items = nullptr;
     AdvanceDesc *d_adv = nullptr;
     uint32_t n_items = 0;
@@ -41,9 +43,10 @@ struct Batch {
         graph = nullptr;
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         cap_stream = nullptr;
-        for (void *q : {(void *)d_views, (void *)d_items, (void *)d_adv})
+        for (void *q : {(void *)d_views, (void *)d_views_t, (void *)d_items, (void *)d_adv})
             if (q) (void)hipFree(q);
         d_views = nullptr;
+        d_views_t = nullptr;
         d_items = nullptr;
         d_adv = nullptr;
         for (Box *b : boxes) {
@@ -57,7 +60,8 @@ struct Batch {
     // one sweep of every box reading buffer `from`
     void launch(int from, uint32_t offset, hipStream_t st) {
         if (fused) {
-            launch_fused_batch(d_views, d_items, n_items, (uint32_t)from, offset, shape, st);
+            launch_fused_batch(timing ? d_views_t : d_views, d_items, n_items, (uint32_t)from, offset,
+                               shape, st);
         } else {
             for (Box *b : boxes) {
                 BoxView v = b->view(from);
@@ -124,7 +128,10 @@ struct Batch {
             cur ^= 1;
             --k;
         }
-        for (Box *b : boxes) b->cur = cur;
+        for (Box *b : boxes) {
+            b->cur = cur;
+            b->canon_in_c = fused;
+        }
         return MPMC_OK;
     }
 
@@ -147,13 +154,19 @@ struct Batch {
         fused = true;
         int rc = build_items();
         if (rc) { shape = keep; fused = keep_fused; return rc; }
+        for (Box *b : boxes) {
+            rc = b->materialize();
+            if (rc) { shape = keep; fused = keep_fused; return rc; }
+        }
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
+        timing = true;
         for (int r = 0; r < 2; ++r) launch(cur, 0, stream);
         (void)hipEventRecord(e0, stream);
         for (int r = 0; r < 6; ++r) launch(cur, 0, stream);
         (void)hipEventRecord(e1, stream);
+        timing = false;
         hipError_t e = hipEventSynchronize(e1);
         float t = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
@@ -243,19 +256,30 @@ extern "C" int mpmc_batch_create(mpmc_batch *out, uint32_t nbox, const uint32_t 
         bt->boxes.push_back(box);
     }
     hipError_t e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
-    std::vector<BoxView> views(2 * nbox);
+    std::vector<BoxView> views(2 * nbox), views_t(2 * nbox);
     std::vector<AdvanceDesc> adv(nbox);
     for (uint32_t b = 0; b < nbox; ++b) {
         views[2 * b] = bt->boxes[b]->view(0);
         views[2 * b + 1] = bt->boxes[b]->view(1);
+        for (int k = 0; k < 2; ++k) {
+            BoxView t = views[2 * b + k];
+            t.cnt_can = nullptr;
+            t.x_can = t.y_can = nullptr;
+            t.tag_can = nullptr;
+            views_t[2 * b + k] = t;
+        }
         const Box *x = bt->boxes[b];
         adv[b] = AdvanceDesc{x->dev, (uint32_t)x->seed, (uint32_t)(x->seed >> 32), (uint32_t)x->g.W,
                              x->g.Lq};
     }
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_views, views.size() * sizeof(BoxView));
+    if (e == hipSuccess) e = hipMalloc((void **)&bt->d_views_t, views.size() * sizeof(BoxView));
     if (e == hipSuccess) e = hipMalloc((void **)&bt->d_adv, adv.size() * sizeof(AdvanceDesc));
     if (e == hipSuccess)
         e = hipMemcpyAsync(bt->d_views, views.data(), views.size() * sizeof(BoxView),
+                           hipMemcpyHostToDevice, bt->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_views_t, views_t.data(), views_t.size() * sizeof(BoxView),
                            hipMemcpyHostToDevice, bt->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(bt->d_adv, adv.data(), adv.size() * sizeof(AdvanceDesc),

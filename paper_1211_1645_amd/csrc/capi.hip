@@ -70,6 +70,10 @@ int mpmc::compute_geometry(Geometry *g, uint32_t N, double eta, double cell_min,
     g->Lq = (int64_t)g->M * g->W;
     g->cap = cell_capacity(w);
     g->CS = g->cap <= 4 ? 4 : 8;
+    // slot indices s * M^2 + c are 32-bit on the device
+    if ((uint64_t)g->M * g->M * g->CS > 0xFFFFFFFFull)
+        return fail(MPMC_EINVAL, "box too large: %u^2 cells x %u slots exceed 32-bit indexing", g->M,
+                    g->CS);
     return MPMC_OK;
 }
 
@@ -107,14 +111,18 @@ void Box::release() {
 
 BoxView Box::view(int from) const {
     BoxView v;
-    v.cnt_in = cnt[from];
-    v.x_in = x[from];
-    v.y_in = y[from];
-    v.tag_in = tag[from];
-    v.cnt_out = cnt[from ^ 1];
-    v.x_out = x[from ^ 1];
-    v.y_out = y[from ^ 1];
-    v.tag_out = tag[from ^ 1];
+    v.cnt_in = P[from].cnt;
+    v.x_in = P[from].x;
+    v.y_in = P[from].y;
+    v.tag_in = P[from].tag;
+    v.cnt_out = P[from ^ 1].cnt;
+    v.x_out = P[from ^ 1].x;
+    v.y_out = P[from ^ 1].y;
+    v.tag_out = P[from ^ 1].tag;
+    v.cnt_can = C.cnt;
+    v.x_can = C.x;
+    v.y_can = C.y;
+    v.tag_can = C.tag;
     v.dev = dev;
     v.M = g.M;
     v.W = (uint32_t)g.W;
@@ -131,10 +139,11 @@ BoxView Box::view(int from) const {
 
 MeasureView Box::mview() const {
     MeasureView m;
-    m.cnt = cnt[cur];
-    m.x = x[cur];
-    m.y = y[cur];
-    m.tag = tag[cur];
+    const CellBuf c = canon();
+    m.cnt = c.cnt;
+    m.x = c.x;
+    m.y = c.y;
+    m.tag = c.tag;
     m.dev = dev;
     m.M = g.M;
     m.W = (uint32_t)g.W;
@@ -165,20 +174,41 @@ int Box::read_scalars() {
     return MPMC_OK;
 }
 
-// Uploads cell lists built on the host (cnt, tag, x, y with stride CS) into
-// buffer 0 and resets the device scalars.
+// Uploads cell lists built on the host (cnt, slot-major tag, x, y) as the
+// canonical state, resets the device scalars, and bins the lists in the
+// grid of the next sweep.
 int Box::upload(const std::vector<uint8_t> &hc, const std::vector<uint32_t> &ht,
                 const std::vector<float> &hx, const std::vector<float> &hy,
                 const DevScalars &s) {
     const size_t nc = (size_t)g.M * g.M, ns = nc * g.CS;
-    cur = 0;
-    HIPCHK(hipMemcpyAsync(cnt[0], hc.data(), nc, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(tag[0], ht.data(), ns * 4, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(x[0], hx.data(), ns * 4, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(y[0], hy.data(), ns * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.cnt, hc.data(), nc, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.tag, ht.data(), ns * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.x, hx.data(), ns * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.y, hy.data(), ns * 4, hipMemcpyHostToDevice, stream));
     host = s;
     HIPCHK(hipMemcpyAsync(dev, &host, sizeof(DevScalars), hipMemcpyHostToDevice, stream));
+    BoxView v = view(1);  // output: P[0]
+    v.cnt_in = C.cnt;
+    v.x_in = C.x;
+    v.y_in = C.y;
+    v.tag_in = C.tag;
+    launch_rebin(v, stream);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
+    cur = 0;
+    canon_in_c = true;
+    return MPMC_OK;
+}
+
+int Box::materialize() {
+    if (canon_in_c) return MPMC_OK;
+    const size_t nc = (size_t)g.M * g.M, ns = nc * g.CS;
+    const CellBuf s = P[cur ^ 1];
+    HIPCHK(hipMemcpyAsync(C.cnt, s.cnt, nc, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.tag, s.tag, ns * 4, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.x, s.x, ns * 4, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(C.y, s.y, ns * 4, hipMemcpyDeviceToDevice, stream));
+    canon_in_c = true;
     return MPMC_OK;
 }
 
@@ -197,7 +227,7 @@ int mpmc::build_cells(const Geometry &g, uint32_t N, const int64_t *X, const int
         const int64_t i = X[t] / g.W, j = Y[t] / g.W;
         const size_t c = (size_t)i + (size_t)g.M * (size_t)j;
         if (hc[c] >= g.cap) return fail(MPMC_EOVERFLOW, "cell %zu exceeds capacity %u", c, g.cap);
-        const size_t o = c * g.CS + hc[c]++;
+        const size_t o = (size_t)hc[c]++ * nc + c;  // slot-major
         ht[o] = t;
         hx[o] = (float)((double)(X[t] - i * g.W) * kQd);
         hy[o] = (float)((double)(Y[t] - j * g.W) * kQd);
@@ -254,11 +284,12 @@ int mpmc::create_box(Box **out, uint32_t N, double eta, uint64_t seed, const mpm
         rc = b->alloc_dev((void **)&(ptr), (bytes));                  \
         if (rc) { b->release(); delete b; return rc; }                \
     } while (0)
-    for (int k = 0; k < 2; ++k) {
-        ALLOC(b->cnt[k], nc);
-        ALLOC(b->x[k], ns * 4);
-        ALLOC(b->y[k], ns * 4);
-        ALLOC(b->tag[k], ns * 4);
+    for (int k = 0; k < 3; ++k) {
+        CellBuf &c = k < 2 ? b->P[k] : b->C;
+        ALLOC(c.cnt, nc);
+        ALLOC(c.x, ns * 4);
+        ALLOC(c.y, ns * 4);
+        ALLOC(c.tag, ns * 4);
     }
     ALLOC(b->dev, sizeof(DevScalars));
     ALLOC(b->hist, K * sizeof(unsigned long long));
@@ -279,7 +310,8 @@ int mpmc::create_box(Box **out, uint32_t N, double eta, uint64_t seed, const mpm
     }
     e = hipMemcpyAsync(b->edges, E.data(), (K + 1) * 4, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->hist, 0, K * 8, b->stream);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(b->cnt[k], 0, nc, b->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(b->P[k].cnt, 0, nc, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->C.cnt, 0, nc, b->stream);
     if (e != hipSuccess) {
         b->release();
         delete b;
@@ -359,6 +391,7 @@ int Box::run_sweeps(uint64_t k) {
             HIPCHK(hipGraphLaunch(graph_exec, stream));
             k -= graph_sweeps;
             host_sweeps += graph_sweeps;
+            canon_in_c = sched != MPMC_SCHED_SIMPLE;
             continue;
         }
         launch_one(cur, 0, stream);
@@ -367,6 +400,7 @@ int Box::run_sweeps(uint64_t k) {
         cur ^= 1;
         --k;
         ++host_sweeps;
+        canon_in_c = sched != MPMC_SCHED_SIMPLE;
     }
     return MPMC_OK;
 }
@@ -503,17 +537,18 @@ extern "C" int mpmc_get_cells(mpmc_box bh, uint8_t *cntp, uint32_t *tagp, float 
     std::vector<uint8_t> hc(nc);
     std::vector<uint32_t> ht(ns);
     std::vector<float> hx(ns), hy(ns);
-    HIPCHK(hipMemcpyAsync(hc.data(), b->cnt[b->cur], nc, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(ht.data(), b->tag[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(hx.data(), b->x[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(hy.data(), b->y[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
+    const CellBuf cb = b->canon();
+    HIPCHK(hipMemcpyAsync(hc.data(), cb.cnt, nc, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(ht.data(), cb.tag, ns * 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(hx.data(), cb.x, ns * 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(hy.data(), cb.y, ns * 4, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     const uint32_t cap = b->g.cap;
     for (size_t c = 0; c < nc; ++c) {
         if (cntp) cntp[c] = hc[c];
         for (uint32_t s = 0; s < cap; ++s) {
             const bool used = s < hc[c];
-            const size_t src = c * b->g.CS + s, dst = c * cap + s;
+            const size_t src = (size_t)s * nc + c, dst = c * cap + s;
             if (tagp) tagp[dst] = used ? ht[src] : 0;
             if (xp) xp[dst] = used ? hx[src] : 0.0f;
             if (yp) yp[dst] = used ? hy[src] : 0.0f;

@@ -327,16 +327,17 @@ extern "C" int mpmc_save(mpmc_box bh, const char *path) {
     std::vector<uint32_t> ht(ns);
     std::vector<float> hx(ns), hy(ns);
     std::vector<unsigned long long> hh(K);
-    HIPCHK(hipMemcpyAsync(hc.data(), b->cnt[b->cur], nc, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(ht.data(), b->tag[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(hx.data(), b->x[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipMemcpyAsync(hy.data(), b->y[b->cur], ns * 4, hipMemcpyDeviceToHost, b->stream));
+    const CellBuf cb = b->canon();
+    HIPCHK(hipMemcpyAsync(hc.data(), cb.cnt, nc, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(ht.data(), cb.tag, ns * 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(hx.data(), cb.x, ns * 4, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(hy.data(), cb.y, ns * 4, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipMemcpyAsync(hh.data(), b->hist, K * 8, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     CkptHeader H;
     memset(&H, 0, sizeof H);
     memcpy(H.magic, kMagic, 8);
-    H.version = 1;
+    H.version = 2;  // slot-major cell lists
     H.N = b->N;
     H.eta = b->eta;
     H.seed = b->seed;
@@ -379,7 +380,7 @@ extern "C" int mpmc_load(mpmc_box *out, const char *path, const mpmc_params *pp)
     FILE *f = fopen(path, "rb");
     if (!f) return fail(MPMC_EIO, "cannot open %s", path);
     CkptHeader H;
-    if (fread(&H, sizeof H, 1, f) != 1 || memcmp(H.magic, kMagic, 8) != 0 || H.version != 1) {
+    if (fread(&H, sizeof H, 1, f) != 1 || memcmp(H.magic, kMagic, 8) != 0 || H.version != 2) {
         fclose(f);
         return fail(MPMC_EIO, "%s is not an MPMC checkpoint", path);
     }

@@ -235,11 +235,11 @@ __device__ inline float log_q(const Gmm &g, float dx, float dy, int Dx, int Dy, 
 
 // ---------------------------------------------------------------------------
 // Features of a disk of cell (ci, cj) at cell-local (x, y), slot `self` of
-// the own cell excluded, from the cell lists (cnt, px, py with stride CS).
+// the own cell excluded, from the slot-major cell lists (cnt, px, py).
 // scr: this lane's 36-float scratch.  Writes bf16 into Xrow[0..31] and/or
 // fp32 into Frow[0..23] (either may be NULL).  Returns the neighbour count.
 __device__ inline int lane_features(const uint8_t *cnt, const float *px, const float *py,
-                                    uint32_t M, uint32_t CS, float w, uint32_t ci, uint32_t cj,
+                                    uint32_t M, float w, uint32_t ci, uint32_t cj,
                                     uint32_t self, float x, float y, float *scr, uint16_t *Xrow,
                                     float *Frow) {
     int n = 0;
@@ -253,8 +253,8 @@ __device__ inline int lane_features(const uint8_t *cnt, const float *px, const f
             const uint32_t m = cnt[nb];
             for (uint32_t s = 0; s < m; ++s) {
                 if (nb == own && s == self) continue;
-                const float dx = (px[nb * CS + s] - x) + cwx;
-                const float dy = (py[nb * CS + s] - y) + cwy;
+                const float dx = (px[slot_at(nb, s, M * M)] - x) + cwx;
+                const float dy = (py[slot_at(nb, s, M * M)] - y) + cwy;
                 const float r2 = r2_f32(dx, dy);
                 if (!(r2 < 9.0f)) continue;
                 if (n < 12) {
@@ -359,13 +359,13 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
             w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
             w2 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
             slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
-            x = v.x_out[cell * v.CS + slot];
-            y = v.y_out[cell * v.CS + slot];
+            x = v.x_out[slot_at(cell, slot, M * M)];
+            y = v.y_out[slot_at(cell, slot, M * M)];
         }
         wave_sync();
         // sorted features into this lane's row of X
         if (act) {
-            const int nf = lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, x, y,
+            const int nf = lane_features(v.cnt_out, v.x_out, v.y_out, M, v.w, ci, cj, slot, x, y,
                                          scr, L.X + 32 * lane, nullptr);
             if (nf > 12) atomicAdd(lv.nfeat_over, 1ull);
         } else {
@@ -379,6 +379,7 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
         Gmm g = gmm_from(OUT + 32 * lane);
         const uint32_t eps_u = (uint32_t)fminf(lv.eps * 4294967296.0f, 4294967295.0f);
         int Dx, Dy;
+        bool drawn = true;  // a Gaussian draw beyond +-1 sigma per axis is rejected
         if (w4.w1 < eps_u) {
             Dx = (int)mulhi32(w4.w2, 2u * (uint32_t)Dm + 1u) - Dm;
             Dy = (int)mulhi32(w4.w3, 2u * (uint32_t)Dm + 1u) - Dm;
@@ -397,14 +398,18 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
             sincosf(6.283185307179586f * u2, &sn, &cs);
             const float ddx = g.mx[k] + expf(g.ax[k]) * rr * cs;
             const float ddy = g.my[k] + expf(g.ay[k]) * rr * sn;
-            Dx = (int)rintf(fminf(fmaxf(ddx, -1.0f), 1.0f) * 4194304.0f);
-            Dy = (int)rintf(fminf(fmaxf(ddy, -1.0f), 1.0f) * 4194304.0f);
+            // rejecting (not clamping) draws beyond the range keeps the
+            // proposal probability of every accepted step equal to q^2 times
+            // the density the Metropolis-Hastings ratio uses
+            drawn = fabsf(ddx) < 1.0f && fabsf(ddy) < 1.0f;
+            Dx = drawn ? (int)rintf(ddx * 4194304.0f) : 0;
+            Dy = drawn ? (int)rintf(ddy * 4194304.0f) : 0;
         }
         const float dxf = (float)Dx * kQ, dyf = (float)Dy * kQ;
         const float lq_f = log_q(g, dxf, dyf, Dx, Dy, Dm, lv.eps, log_u);
         // geometry in q units: exact
         const int U = (int)(x * 4194304.0f) + Dx, V = (int)(y * 4194304.0f) + Dy;
-        bool ok = act && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
+        bool ok = act && drawn && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
         const float xn = (float)U * kQ, yn = (float)V * kQ;
         if (ok) {
             for (int dj = -1; dj <= 1 && ok; ++dj)
@@ -416,8 +421,8 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
                     const uint32_t m = v.cnt_out[nb];
                     for (uint32_t s = 0; s < m; ++s) {
                         if (nb == cell && s == slot) continue;
-                        const float ddx = (v.x_out[nb * v.CS + s] - xn) + cwx;
-                        const float ddy = (v.y_out[nb * v.CS + s] - yn) + cwy;
+                        const float ddx = (v.x_out[slot_at(nb, s, M * M)] - xn) + cwx;
+                        const float ddy = (v.y_out[slot_at(nb, s, M * M)] - yn) + cwy;
                         if (overlap_f32(ddx, ddy)) { ok = false; break; }
                     }
                 }
@@ -425,7 +430,7 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
         // reverse density at x' (every lane takes part in the wave GEMMs)
         wave_sync();
         if (ok) {
-            lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, xn, yn, scr,
+            lane_features(v.cnt_out, v.x_out, v.y_out, M, v.w, ci, cj, slot, xn, yn, scr,
                           L.X + 32 * lane, nullptr);
         } else {
             for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = 0;
@@ -438,8 +443,8 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
             const float lq_r = log_q(gr, -dxf, -dyf, -Dx, -Dy, Dm, lv.eps, log_u);
             const float ua = ((float)(w2.w3 >> 8) + 0.5f) * (1.0f / 16777216.0f);
             if (logf(ua) < lq_r - lq_f) {
-                v.x_out[cell * v.CS + slot] = xn;
-                v.y_out[cell * v.CS + slot] = yn;
+                v.x_out[slot_at(cell, slot, M * M)] = xn;
+                v.y_out[slot_at(cell, slot, M * M)] = yn;
                 ++accepts;
             }
         }
@@ -490,7 +495,7 @@ __global__ void __launch_bounds__(128) k_pass_collect(BoxView v, uint32_t pass, 
         for (uint32_t tr = 0; tr < v.n_trial && n > 0; ++tr) {
             const Words w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
             const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
-            const uint32_t k = cell * v.CS + slot;
+            const uint32_t k = slot_at(cell, slot, M * M);
             const float dx = step_from_word(w4.w1, v.step_m), dy = step_from_word(w4.w2, v.step_m);
             const float x = v.x_out[k], y = v.y_out[k];
             const float xn = x + dx, yn = y + dy;
@@ -506,15 +511,15 @@ __global__ void __launch_bounds__(128) k_pass_collect(BoxView v, uint32_t pass, 
                     const uint32_t m = v.cnt_out[nb];
                     for (uint32_t s = 0; s < m; ++s) {
                         if (nb == cell && s == slot) continue;
-                        const float ddx = (v.x_out[nb * v.CS + s] - xn) + cwx;
-                        const float ddy = (v.y_out[nb * v.CS + s] - yn) + cwy;
+                        const float ddx = (v.x_out[slot_at(nb, s, M * M)] - xn) + cwx;
+                        const float ddy = (v.y_out[slot_at(nb, s, M * M)] - yn) + cwy;
                         if (overlap_f32(ddx, ddy)) { bad = true; break; }
                     }
                 }
             if (bad) continue;
             const unsigned long long idx = atomicAdd(cv.count, 1ull);
             if (idx < cv.cap) {
-                lane_features(v.cnt_out, v.x_out, v.y_out, M, v.CS, v.w, ci, cj, slot, x, y, scr,
+                lane_features(v.cnt_out, v.x_out, v.y_out, M, v.w, ci, cj, slot, x, y, scr,
                               nullptr, cv.F + idx * 24);
                 cv.D[2 * idx] = dx;
                 cv.D[2 * idx + 1] = dy;
@@ -533,11 +538,11 @@ __global__ void k_features(const uint8_t *cnt, const float *px, const float *py,
                            uint32_t M, uint32_t CS, float w, const int32_t *row_of, float *F) {
     __shared__ float scr_all[256 * 36];
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cell = gid / CS, s = gid % CS;
-    if (cell >= M * M || s >= cnt[cell]) return;
-    const int32_t r = row_of[tag[cell * CS + s]];
+    const uint32_t s = gid / (M * M), cell = gid - s * (M * M);
+    if (s >= CS || s >= cnt[cell]) return;
+    const int32_t r = row_of[tag[gid]];
     if (r < 0) return;
-    lane_features(cnt, px, py, M, CS, w, cell % M, cell / M, s, px[cell * CS + s], py[cell * CS + s],
+    lane_features(cnt, px, py, M, w, cell % M, cell / M, s, px[gid], py[gid],
                   scr_all + 36 * threadIdx.x, nullptr, F + (size_t)r * 24);
 }
 
@@ -943,12 +948,15 @@ extern "C" int mpmc_learner_collect(mpmc_learner lh, mpmc_box bh, uint64_t sweep
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
     for (uint64_t s = 0; s < sweeps; ++s) {
         BoxView v = b->view(b->cur);
-        launch_simple_sweep_rebin_only(v, b->stream);
-        for (uint32_t p = 0; p < 4; ++p) k_pass_collect<<<(na + 127) / 128, 128, 0, b->stream>>>(v, p, cv);
+        const BoxView pv = in_place(v);
+        for (uint32_t p = 0; p < 4; ++p) k_pass_collect<<<(na + 127) / 128, 128, 0, b->stream>>>(pv, p, cv);
+        v.offset = 1;  // binned for the next sweep
+        launch_rebin(v, b->stream);
         launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
                        1, b->stream);
         HIPCHK(hipGetLastError());
         b->cur ^= 1;
+        b->canon_in_c = false;
     }
     if (n_total) {
         unsigned long long c = 0;
@@ -1066,8 +1074,9 @@ extern "C" int mpmc_learned_features(mpmc_box bh, const uint32_t *tags, uint32_t
     if (e == hipSuccess) e = hipMemsetAsync(dF, 0, (size_t)n * 24 * 4, b->stream);
     if (e == hipSuccess) {
         const uint32_t tot = b->g.M * b->g.M * b->g.CS;
-        k_features<<<(tot + 255) / 256, 256, 0, b->stream>>>(b->cnt[b->cur], b->x[b->cur], b->y[b->cur],
-                                                             b->tag[b->cur], b->g.M, b->g.CS, b->g.w, drow, dF);
+        const CellBuf cb = b->canon();
+        k_features<<<(tot + 255) / 256, 256, 0, b->stream>>>(cb.cnt, cb.x, cb.y, cb.tag, b->g.M, b->g.CS,
+                                                             b->g.w, drow, dF);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(F, dF, (size_t)n * 24 * 4, hipMemcpyDeviceToHost, b->stream);
@@ -1100,12 +1109,15 @@ extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, floa
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
     for (uint64_t s = 0; s < k; ++s) {
         BoxView v = b->view(b->cur);
-        launch_simple_sweep_rebin_only(v, b->stream);
-        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + 63) / 64, 64, lds, b->stream>>>(v, p, lv);
+        const BoxView pv = in_place(v);
+        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + 63) / 64, 64, lds, b->stream>>>(pv, p, lv);
+        v.offset = 1;  // binned for the next sweep
+        launch_rebin(v, b->stream);
         launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
                        1, b->stream);
         HIPCHK(hipGetLastError());
         b->cur ^= 1;
+        b->canon_in_c = false;
     }
     if (trials || accepts) {
         rc = b->read_scalars();

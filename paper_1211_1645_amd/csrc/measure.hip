@@ -28,11 +28,11 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
     const uint32_t M = m.M;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < m.N && (!sel || sel[t])) {
-        const uint32_t cell = loc[t] / m.CS, s = loc[t] % m.CS;
+        const uint32_t NC = M * M, s = loc[t] / NC, cell = loc[t] - s * NC;
         const uint32_t ci = cell % M, cj = cell / M;
         const float e0 = E[0], eK = E[K];
         const float rmax = sqrtf(eK) * 1.0001f + 1e-4f;  // conservative reach
-        const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
+        const float xi = m.x[loc[t]], yi = m.y[loc[t]];
         for (int dj = -h; dj <= h; ++dj) {
             // smallest |dy| to any disk of row dj: skip rows out of reach
             const float gy = dj > 1 ? (float)(dj - 1) * m.w + (m.w - yi)
@@ -47,8 +47,8 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
                 const uint32_t mm = m.cnt[nb];
                 for (uint32_t q = 0; q < mm; ++q) {
                     if (di == 0 && dj == 0 && q == s) continue;
-                    const float dx = (m.x[nb * m.CS + q] - xi) + cwx;
-                    const float dy = (m.y[nb * m.CS + q] - yi) + cwy;
+                    const float dx = (m.x[slot_at(nb, q, NC)] - xi) + cwx;
+                    const float dy = (m.y[slot_at(nb, q, NC)] - yi) + cwy;
                     const float r2 = r2_f32(dx, dy);
                     if (!(r2 >= e0) || !(r2 < eK)) continue;
                     // start from the square-root estimate, then settle on the
@@ -67,12 +67,12 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
         if (bins[k]) atomicAdd(&hist[k], (unsigned long long)bins[k]);
 }
 
-// Slot of every disk by tag: loc[tag] = cell * CS + slot.
+// Slot of every disk by tag: loc[tag] = slot_at(cell, slot, M * M).
 __global__ void __launch_bounds__(256) k_locate(MeasureView m, uint32_t *loc) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cell = gid / m.CS, s = gid % m.CS;
-    if (cell >= m.M * m.M || s >= m.cnt[cell]) return;
-    const uint32_t tg = m.tag[cell * m.CS + s];
+    const uint32_t NC = m.M * m.M, s = gid / NC, cell = gid - s * NC;
+    if (s >= m.CS || s >= m.cnt[cell]) return;
+    const uint32_t tg = m.tag[gid];
     if (tg < m.N) loc[tg] = gid;
 }
 
@@ -107,12 +107,13 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
                                               uint32_t *fail, const uint32_t *loc) {
     const uint32_t M = m.M;
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cell = gid < m.N ? loc[gid] / m.CS : 0, s = gid < m.N ? loc[gid] % m.CS : 0;
+    const uint32_t NC = M * M, at = gid < m.N ? loc[gid] : 0;
+    const uint32_t s = at / NC, cell = at - s * NC;
     double pr = 0.0, pi = 0.0;
     if (gid < m.N) {
         const uint32_t ci = cell % M, cj = cell / M;
-        const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
-        const uint32_t ti = m.tag[cell * m.CS + s];
+        const float xi = m.x[at], yi = m.y[at];
+        const uint32_t ti = m.tag[at];
         Nb6 b;
 #pragma unroll
         for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
@@ -123,10 +124,10 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
                 const uint32_t mm = m.cnt[nb];
                 for (uint32_t t = 0; t < mm; ++t) {
                     if (di == 0 && dj == 0 && t == s) continue;
-                    const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
-                    const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
+                    const float dx = (m.x[slot_at(nb, t, NC)] - xi) + cwx;
+                    const float dy = (m.y[slot_at(nb, t, NC)] - yi) + cwy;
                     const float r2 = r2_f32(dx, dy);
-                    const uint32_t tg = m.tag[nb * m.CS + t];
+                    const uint32_t tg = m.tag[slot_at(nb, t, NC)];
                     if (!nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
                     b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
 #pragma unroll
@@ -189,7 +190,7 @@ __global__ void __launch_bounds__(256) k_psi6_field(MeasureView m, const float *
         for (int di = -1; di <= 1; ++di) {
             const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
             for (uint32_t t = 0; t < m.cnt[nb]; ++t) {
-                const uint32_t tg = m.tag[nb * m.CS + t];
+                const uint32_t tg = m.tag[slot_at(nb, t, M * M)];
                 sr += re[tg];
                 si += im[tg];
                 ++n;
@@ -218,8 +219,8 @@ __global__ void __launch_bounds__(256) k_validate(MeasureView m, uint32_t *tag_s
         uint32_t n = m.cnt[cell];
         if (n > m.cap) { ++bad; n = m.cap; }
         for (uint32_t s = 0; s < n; ++s) {
-            const float xi = m.x[cell * m.CS + s], yi = m.y[cell * m.CS + s];
-            const uint32_t tg = m.tag[cell * m.CS + s];
+            const float xi = m.x[slot_at(cell, s, M * M)], yi = m.y[slot_at(cell, s, M * M)];
+            const uint32_t tg = m.tag[slot_at(cell, s, M * M)];
             if (!(xi >= 0.0f && xi < m.w && yi >= 0.0f && yi < m.w)) ++bad;
             if (tg < m.N) atomicAdd(&tag_seen[tg], 1u); else ++bad;
             for (int dj = -1; dj <= 1; ++dj)
@@ -230,8 +231,8 @@ __global__ void __launch_bounds__(256) k_validate(MeasureView m, uint32_t *tag_s
                     mm = mm > m.cap ? m.cap : mm;
                     for (uint32_t t = 0; t < mm; ++t) {
                         if (di == 0 && dj == 0 && t == s) continue;
-                        const float dx = (m.x[nb * m.CS + t] - xi) + cwx;
-                        const float dy = (m.y[nb * m.CS + t] - yi) + cwy;
+                        const float dx = (m.x[slot_at(nb, t, M * M)] - xi) + cwx;
+                        const float dy = (m.y[slot_at(nb, t, M * M)] - yi) + cwy;
                         if (overlap_f32(dx, dy)) ++ov;
                     }
                 }
@@ -257,11 +258,11 @@ void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st) {
 __global__ void __launch_bounds__(256) k_positions(MeasureView m, long long *X, long long *Y) {
     const uint32_t M = m.M;
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t cell = gid / m.CS, s = gid % m.CS;
-    if (cell >= M * M || s >= m.cnt[cell]) return;
-    const long long U = (long long)(m.x[cell * m.CS + s] * 4194304.0f);
-    const long long V = (long long)(m.y[cell * m.CS + s] * 4194304.0f);
-    const uint32_t tg = m.tag[cell * m.CS + s];
+    const uint32_t s = gid / (M * M), cell = gid - s * (M * M);
+    if (s >= m.CS || s >= m.cnt[cell]) return;
+    const long long U = (long long)(m.x[gid] * 4194304.0f);
+    const long long V = (long long)(m.y[gid] * 4194304.0f);
+    const uint32_t tg = m.tag[gid];
     if (tg >= m.N) return;
     X[tg] = ((long long)(cell % M) * m.W + U + m.Sx) % m.Lq;
     Y[tg] = ((long long)(cell / M) * m.W + V + m.Sy) % m.Lq;

@@ -121,8 +121,20 @@ struct DevScalars {
     unsigned long long slot_accepts[kCountSlots];
 };
 
-// Everything a sweep kernel needs; buffers are the SoA cell lists with slot
-// stride CS (cnt[c], x[c*CS + s], y[..], tag[..]).
+// Cell lists are stored slot-major: slot s of cell c is element s * NC + c
+// of the x, y and tag arrays (NC = M * M cells, CS slots allocated per cell).
+// Only slots below the cell's count hold disks; the rest keep stale values
+// and are never read, so a wave that walks consecutive cells reads and
+// writes consecutive words of the slots in use and nothing else.
+__host__ __device__ __forceinline__ uint32_t slot_at(uint32_t c, uint32_t s, uint32_t NC) {
+    return s * NC + c;
+}
+
+// Everything a sweep kernel needs (cnt[c], x/y/tag slot-major as above):
+// the cell lists the sweep reads, binned in its own grid (in); the lists
+// binned for the next sweep that it writes (out); and where it writes the
+// box's canonical state after the sweep, in this sweep's grid (can; NULL
+// for launches that only time the kernel).
 struct BoxView {
     const uint8_t *cnt_in;
     const float *x_in, *y_in;
@@ -130,6 +142,9 @@ struct BoxView {
     uint8_t *cnt_out;
     float *x_out, *y_out;
     uint32_t *tag_out;
+    uint8_t *cnt_can;
+    float *x_can, *y_can;
+    uint32_t *tag_can;
     DevScalars *dev;
     uint32_t M, W, cap, CS;
     uint32_t step_m, n_trial;

@@ -19,13 +19,20 @@ struct Geometry {
     float w;       // cell width (exact fp32)
     int64_t Lq;    // simulated side M W in q units
     uint32_t cap;  // disks a cell can hold
-    uint32_t CS;   // slot stride of the cell arrays (4 or 8)
+    uint32_t CS;   // slots allocated per cell (4 or 8), stored slot-major
 };
 
 int compute_geometry(Geometry *g, uint32_t N, double eta, double cell_min, uint32_t step_m);
 int build_cells(const Geometry &g, uint32_t N, const int64_t *X, const int64_t *Y,
                 std::vector<uint8_t> &hc, std::vector<uint32_t> &ht, std::vector<float> &hx,
                 std::vector<float> &hy);
+
+// One set of SoA cell lists (slot-major x, y, tag).
+struct CellBuf {
+    uint8_t *cnt = nullptr;
+    uint32_t *tag = nullptr;
+    float *x = nullptr, *y = nullptr;
+};
 
 struct Box {
     uint32_t N = 0;
@@ -35,11 +42,16 @@ struct Box {
     Geometry g{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    // double-buffered SoA cell lists; `cur` holds the current state
-    uint8_t *cnt[2] = {nullptr, nullptr};
-    float *x[2] = {nullptr, nullptr}, *y[2] = {nullptr, nullptr};
-    uint32_t *tag[2] = {nullptr, nullptr};
+    // P[cur]: the cell lists the next sweep reads, already binned in its
+    // shifted grid; P[cur ^ 1]: the other buffer.  The canonical state (the
+    // box after its last sweep, in that sweep's grid) is C when canon_in_c,
+    // else P[cur ^ 1]: the last sweep's input, updated in place by the
+    // simple and learned schedules.
+    CellBuf P[2], C;
     int cur = 0;
+    bool canon_in_c = true;
+    CellBuf canon() const { return canon_in_c ? C : P[cur ^ 1]; }
+    int materialize();  // moves the canonical state into C
     bool placed = true;
     DevScalars *dev = nullptr;
     DevScalars host{};

@@ -30,8 +30,14 @@ __device__ __forceinline__ void count_trials(DevScalars *dev, uint32_t t, uint32
 }
 
 // sweep_simple.hip
+// passes in place on v's input lists, then the re-bin of them into v's
+// output lists for sweep dev->sweep + offset + 1
 void launch_simple_sweep(const BoxView &v, hipStream_t st);
-void launch_simple_sweep_rebin_only(const BoxView &v, hipStream_t st);
+// the re-bin alone: v's input lists into v's output lists, binned in the
+// grid of sweep dev->sweep + offset
+void launch_rebin(const BoxView &v, hipStream_t st);
+// v with its output lists set to its input lists
+BoxView in_place(const BoxView &v);
 void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,
                     long long Lq, uint32_t count, hipStream_t st);
 
@@ -61,7 +67,7 @@ struct MeasureView {
     long long Sx, Sy, Lq;
 };
 // h: stencil half-width in cells (1 when w covers the histogram range)
-// Kernels over disks take loc[tag] = cell * CS + slot (launch_locate).
+// Kernels over disks take loc[tag] = slot_at(cell, slot, M * M) (launch_locate).
 void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st);
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
                          unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,

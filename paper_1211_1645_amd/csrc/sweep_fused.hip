@@ -1,14 +1,20 @@
 // sweep_fused.hip — one kernel launch per MPMC sweep (Sec. II.B).
 //
-// A workgroup owns a TILE x TILE block of cells of the shifted grid.  It
-// re-bins the block plus a halo of 4 cells into LDS straight from the
-// previous sweep's cell lists, runs all four colour sub-sweeps on LDS with a
-// barrier between them, and writes back only its own block.  Pass p (0..3)
-// updates the cells of its colour within 3 - p cells of the block: exactly
-// the cells whose state the block's final state depends on, so the halo
-// work reproduces what the neighbouring workgroups compute.  Because every
-// random number is keyed by (seed, sweep, cell, trial), the recomputed halo
-// is identical to theirs and the trajectory does not depend on TILE.
+// The cell lists a sweep reads are already binned in that sweep's shifted
+// grid (the previous launch re-binned them).  A workgroup owns a TILE x TILE
+// block of cells.  It loads the block, extended by one row and column on
+// the +x and +y sides, plus a halo of 4 cells into LDS, runs all four
+// colour sub-sweeps there with a barrier between them, and then
+//   - writes its own block's final state (the canonical state of the box
+//     after this sweep), and
+//   - re-bins the extended block into the next sweep's grid and writes the
+//     block's cells of that grid: new cell (I, J) draws only on old cells
+//     (I..I+1, J..J+1), all inside the extended block.
+// Pass p (0..3) updates the cells of its colour within 3 - p cells of the
+// extended block: exactly the cells its final state depends on, so the
+// halo work reproduces what the neighbouring workgroups compute.  Every
+// random number is keyed by (seed, sweep, cell, trial), so the recomputed
+// halo is identical to theirs and the trajectory does not depend on TILE.
 //
 // In LDS a cell keeps its (at most 4) disks as centred offsets s = u - c,
 // c = floor(W/2) q, so |s| <= w/2 and, for a trial position s' and a
@@ -18,10 +24,33 @@
 // cell-local formula.  Empty slots hold a far sentinel so every pair test
 // runs without branches.  Cells are stored by colour plane so that the
 // lanes of a wave, which work on cells of one colour, read consecutive
-// 16-byte records.
+// records.
 #include "mpmc_kernels.hpp"
 
 namespace mpmc {
+
+#define MPMC_GLOBAL __attribute__((address_space(1)))
+
+// BoxView with its buffers typed as global memory.  A view read from memory
+// (the batch work list) would otherwise leave generic pointers behind, and
+// every access through them would compile to a flat instruction.
+struct GlobalView {
+    const MPMC_GLOBAL uint8_t *cnt_in;
+    const MPMC_GLOBAL float *x_in, *y_in;
+    const MPMC_GLOBAL uint32_t *tag_in;
+    MPMC_GLOBAL uint8_t *cnt_out;
+    MPMC_GLOBAL float *x_out, *y_out;
+    MPMC_GLOBAL uint32_t *tag_out;
+    MPMC_GLOBAL uint8_t *cnt_can;
+    MPMC_GLOBAL float *x_can, *y_can;
+    MPMC_GLOBAL uint32_t *tag_can;
+    MPMC_GLOBAL DevScalars *dev;
+    uint32_t M, W, cap, CS;
+    uint32_t step_m, n_trial;
+    float w;
+    uint32_t seed_lo, seed_hi;
+    uint32_t offset;
+};
 
 namespace {
 constexpr int kHalo = 4;
@@ -29,22 +58,35 @@ constexpr float kFar = 1.0e6f;  // sentinel offset of an empty slot
 
 template <int TILE>
 struct Lds {
-    static constexpr int R = TILE + 2 * kHalo;  // region side (new grid), even
+    static constexpr int RL = TILE + 2 * kHalo + 1;  // loaded region side
+    static constexpr int R = RL + 1;                 // allocated side (even)
     static constexpr int NC = R * R;
-    static constexpr int NO = (R + 1) * (R + 1);  // old-grid region
-    static constexpr int NA = (R / 2 - 1) * (R / 2 - 1);  // most active cells in a pass
+    static constexpr int TE = TILE + 1;              // extended block side
+    static constexpr int HH = (R / 2) * (R / 2);     // cells of one colour plane
     float4 x[NC];
     float4 y[NC];
     uint8_t cnt[NC];
-    uint16_t gcnt[NO];   // per old cell: disks per wrap class, 3 bits each
-    uint16_t list[NA];   // non-empty active cells of the current pass
-    uint32_t wsum[17];   // per-wave counts for the compaction scan
+    union {
+        uint16_t list[4][HH];   // passes: the non-empty cells each pass updates
+        uint16_t gcnt[TE * TE]; // re-bin: per old cell, disks per wrap class, 3 bits each
+    };
+    uint32_t wsum[4][16];  // per-pass, per-wave counts for the compaction scan
+    uint32_t big;          // some region cell holds more than two disks
 };
 
 // LDS index of region cell (rx, ry): colour plane, then row-major in plane.
 template <int R>
 __device__ __forceinline__ int pidx(int rx, int ry) {
     return ((rx & 1) | ((ry & 1) << 1)) * (R / 2) * (R / 2) + (rx >> 1) + (R / 2) * (ry >> 1);
+}
+
+// threadIdx.x through an opaque move: in the batch kernel's work loop the
+// values derived from it are then recomputed for each item instead of being
+// hoisted out of the loop and kept live in registers throughout.
+__device__ __forceinline__ int opaque_tid() {
+    int t;
+    __asm__ volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
 }
 
 __device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t M) {
@@ -69,9 +111,6 @@ __device__ __forceinline__ float4 put4(float4 v, uint32_t s, float f) {
 __device__ __forceinline__ float comp4(const float4 &v, int s) {
     return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
-__device__ __forceinline__ uint32_t compu4(const uint4 &v, int s) {
-    return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
-}
 }  // namespace
 
 struct PassCtx {
@@ -79,45 +118,114 @@ struct PassCtx {
     uint32_t gx0, gy0;
     int own_x, own_y;
     float cen;
+    bool big;
 };
 
-// One colour sub-sweep over the LDS region: pass p updates the cells of
-// colour (CX, CY) with region coordinates in [p+1, R-p-1).  The non-empty
-// ones are compacted into a list first; each is then visited by one lane.
-template <int TILE, int THREADS, int CX, int CY>
-__device__ __forceinline__ void run_pass(Lds<TILE> &L, const BoxView &v, const PassCtx &ctx,
-                                         int p, uint32_t &trials, uint32_t &accepts) {
-    constexpr int R = Lds<TILE>::R, H = R / 2, PB = (CX | (CY << 1)) * H * H;
-    const int lo = p + 1, hi = R - p - 1;
-    const uint32_t M = v.M;
-    int total = 0;
-    for (int base = 0; base < H * H; base += THREADS) {
-        const int a = base + (int)threadIdx.x;
-        const bool cand = a < H * H;
-        const int ax = a % H, ay = a / H;
-        const int rx = 2 * ax + CX, ry = 2 * ay + CY;
-        const bool live = cand && rx >= lo && rx < hi && ry >= lo && ry < hi &&
-                          L.cnt[PB + (cand ? a : 0)] != 0;
-        const unsigned long long bal = __ballot(live);
-        const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-        if (lane == 0) L.wsum[wave] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        uint32_t before = 0, all = 0;
+// Does a disk at centred offsets (xn, yn) of region cell (CX + 2 ax, CY + 2 ay)
+// overlap any disk of its 3 x 3 neighbourhood other than slot `slot` of its
+// own cell (whose records are mx, my)?  Only slots below SL are tested: the
+// caller knows that no cell of the region holds more than SL disks, and the
+// empty slots hold the far sentinel.
+template <int SL, int H, int CX, int CY, typename LdsT>
+__device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_t slot,
+                                             const float4 &mx, const float4 &my, float xn,
+                                             float yn, float w) {
+    const float ax3[3] = {xn + w, xn, xn - w};  // q_di = s' - di w
+    const float ay3[3] = {yn + w, yn, yn - w};
+    bool bad = false;
 #pragma unroll
-        for (uint32_t q = 0; q < THREADS / 64; ++q) {
-            const uint32_t cq = L.wsum[q];
-            before += q < wave ? cq : 0u;
-            all += cq;
+    for (int k = 0; k < 9; ++k) {
+        const int di = k % 3 - 1, dj = k / 3 - 1;
+        const float gx = ax3[k % 3], gy = ay3[k / 3];
+        if (k == 4) {
+            // own cell: every slot but the moving one
+            bad |= slot != 0 && overlap_f32(mx.x - gx, my.x - gy);
+            bad |= slot != 1 && overlap_f32(mx.y - gx, my.y - gy);
+            if (SL > 2) {
+                bad |= slot != 2 && overlap_f32(mx.z - gx, my.z - gy);
+                bad |= slot != 3 && overlap_f32(mx.w - gx, my.w - gy);
+            }
+            continue;
         }
-        const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-        if (live) L.list[total + before + rank] = (uint16_t)a;
-        total += (int)all;
+        // neighbour (rx + di, ry + dj): its colour plane and in-plane offset
+        // are compile-time constants for this colour
+        const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
+        const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
+        const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
+        if (SL > 2) {
+            const float4 qx = L.x[ne], qy = L.y[ne];
+            bad |= overlap_f32(qx.x - gx, qy.x - gy);
+            bad |= overlap_f32(qx.y - gx, qy.y - gy);
+            bad |= overlap_f32(qx.z - gx, qy.z - gy);
+            bad |= overlap_f32(qx.w - gx, qy.w - gy);
+        } else {
+            const float2 qx = *reinterpret_cast<const float2 *>(&L.x[ne]);
+            const float2 qy = *reinterpret_cast<const float2 *>(&L.y[ne]);
+            bad |= overlap_f32(qx.x - gx, qy.x - gy);
+            bad |= overlap_f32(qx.y - gx, qy.y - gy);
+        }
+        // one row of neighbour records in flight at a time keeps the
+        // register budget of four waves per SIMD
+        if (k == 2 || k == 5) __asm__ volatile("" ::: "memory");
+    }
+    return bad;
+}
+
+// Lists, for all four passes at once, the non-empty cells each pass updates
+// (colour col[p], region coordinates in [p+1, RL-p-1)); total[p] is the
+// length of list p, the same in every thread.
+template <int TILE, int THREADS>
+__device__ __forceinline__ void compact_passes(Lds<TILE> &L, int tid, const uint32_t col[4],
+                                               int total[4]) {
+    constexpr int RL = Lds<TILE>::RL, H = Lds<TILE>::R / 2, HH = H * H;
+    const uint32_t lane = (uint32_t)tid & 63u, wave = (uint32_t)tid >> 6;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) total[p] = 0;
+    for (int base = 0; base < HH; base += THREADS) {
+        const int a = base + tid;
+        const bool cand = a < HH;
+        const int ax = a % H, ay = a / H;
+        unsigned long long bal[4];
+        bool live[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int rx = 2 * ax + (int)(col[p] & 1u), ry = 2 * ay + (int)(col[p] >> 1);
+            const int lo = p + 1, hi = RL - p - 1;
+            live[p] = cand && rx >= lo && rx < hi && ry >= lo && ry < hi &&
+                      L.cnt[(int)col[p] * HH + (cand ? a : 0)] != 0;
+            bal[p] = __ballot(live[p]);
+            if (lane == 0) L.wsum[p][wave] = (uint32_t)__popcll(bal[p]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            uint32_t before = 0, all = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < THREADS / 64; ++q) {
+                const uint32_t cq = L.wsum[p][q];
+                before += q < wave ? cq : 0u;
+                all += cq;
+            }
+            const uint32_t rank = (uint32_t)__popcll(bal[p] & ((1ull << lane) - 1ull));
+            if (live[p]) L.list[p][total[p] + (int)(before + rank)] = (uint16_t)a;
+            total[p] += (int)all;
+        }
         __syncthreads();
     }
+}
+
+// One colour sub-sweep over the LDS region: pass p updates the cells of
+// list p (colour (CX, CY)), one lane per cell.
+template <int TILE, int THREADS, int CX, int CY, typename View>
+__device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const PassCtx &ctx,
+                                         int tid, int p, int total, uint32_t &trials,
+                                         uint32_t &accepts) {
+    constexpr int H = Lds<TILE>::R / 2, PB = (CX | (CY << 1)) * H * H;
+    const uint32_t M = v.M;
     const float w = v.w, cen = ctx.cen;
     const float lo_b = -cen, hi_b = w - cen;  // in-cell range of centred offsets
-    for (int j = threadIdx.x; j < total; j += THREADS) {
-        const int a = L.list[j];
+    for (int j = tid; j < total; j += THREADS) {
+        const int a = L.list[p][j];
         const int ax = a % H, ay = a / H;
         const int rx = 2 * ax + CX, ry = 2 * ay + CY;
         const int e = PB + a;
@@ -147,35 +255,8 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const BoxView &v, const P
             const float yn = pick4(my, slot) + step_from_word(w4.w2, v.step_m);
             if (own) ++trials;
             const bool inside = xn >= lo_b && xn < hi_b && yn >= lo_b && yn < hi_b;
-            const float ax3[3] = {xn + w, xn, xn - w};  // q_di = s' - di w
-            const float ay3[3] = {yn + w, yn, yn - w};
-            bool bad = false;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int di = k % 3 - 1, dj = k / 3 - 1;
-                const float gx = ax3[k % 3], gy = ay3[k / 3];
-                if (k == 4) {
-                    // own cell: every slot but the moving one
-                    bad |= slot != 0 && overlap_f32(mx.x - gx, my.x - gy);
-                    bad |= slot != 1 && overlap_f32(mx.y - gx, my.y - gy);
-                    bad |= slot != 2 && overlap_f32(mx.z - gx, my.z - gy);
-                    bad |= slot != 3 && overlap_f32(mx.w - gx, my.w - gy);
-                    continue;
-                }
-                // neighbour (rx + di, ry + dj): its colour plane and in-plane
-                // offset are compile-time constants for this colour
-                            const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
-                const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
-                const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
-                const float4 qx = L.x[ne], qy = L.y[ne];
-                bad |= overlap_f32(qx.x - gx, qy.x - gy);
-                bad |= overlap_f32(qx.y - gx, qy.y - gy);
-                bad |= overlap_f32(qx.z - gx, qy.z - gy);
-                bad |= overlap_f32(qx.w - gx, qy.w - gy);
-                // one row of neighbour records in flight at a time keeps the
-                // register budget of four waves per SIMD
-                if (k == 2 || k == 5) __asm__ volatile("" ::: "memory");
-            }
+            const bool bad = ctx.big ? overlaps_any<4, H, CX, CY>(L, base_ax, slot, mx, my, xn, yn, w)
+                                     : overlaps_any<2, H, CX, CY>(L, base_ax, slot, mx, my, xn, yn, w);
             const bool acc = inside && !bad;
             mx = acc ? put4(mx, slot, xn) : mx;
             my = acc ? put4(my, slot, yn) : my;
@@ -186,118 +267,96 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const BoxView &v, const P
     }
 }
 
-// The work of one tile: re-bin, four colour passes, write-back, counts.
-template <int TILE, int THREADS>
-__device__ __forceinline__ void fused_tile(Lds<TILE> &L, const BoxView &v, uint32_t I0,
+// The work of one tile: load, four colour passes, canonical write-back,
+// re-bin into the next sweep's grid, counts.
+template <int TILE, int THREADS, typename View>
+__device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid, uint32_t I0,
                                            uint32_t J0) {
-    constexpr int R = Lds<TILE>::R;
-    const uint32_t M = v.M;
+    constexpr int RL = Lds<TILE>::RL, R = Lds<TILE>::R, TE = Lds<TILE>::TE;
+    constexpr int NL = RL * RL, NIT = (NL + THREADS - 1) / THREADS;  // loaded cells per thread
+    constexpr int NE = TE * TE, NEIT = (NE + THREADS - 1) / THREADS;  // extended-block cells
+    const uint32_t M = v.M, NC = M * M;
     const int own_x = (M - I0 < (uint32_t)TILE) ? (int)(M - I0) : TILE;
     const int own_y = (M - J0 < (uint32_t)TILE) ? (int)(M - J0) : TILE;
 
     const uint64_t sweep = v.dev->sweep + v.offset;
     const SweepDraws d = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
-    const float sx = (float)d.kx * kQ, sy = (float)d.ky * kQ;
     const float w = v.w;
     const float cen = (float)(v.W >> 1) * kQ;  // centring offset c
     const uint32_t gx0 = wrap_add(I0, -kHalo, M), gy0 = wrap_add(J0, -kHalo, M);
 
-    // ---- re-bin the region from the previous sweep's cell lists ----------
-    // New cell (I, J) takes the disks of old (I, J) that do not wrap, then
-    // those of (I+1, J) wrapping in x only, (I, J+1) in y only, (I+1, J+1)
-    // in both, each in old slot order.  Old region cell (ox, oy) is global
-    // old cell (gx0 + ox, gy0 + oy) and feeds new region cells (ox - wx,
-    // oy - wy).  Step 1 classifies every old disk once and counts the four
-    // wrap classes per old cell; step 2 scatters each disk to its slot,
-    // whose index follows from the class counts of the cells before it in
-    // the new cell's order.  Own-block counts and tags are final here.
-    constexpr int RO = R + 1;
-    const float4 far4 = make_float4(kFar, kFar, kFar, kFar);
-    for (int e = threadIdx.x; e < RO * RO; e += THREADS) {
-        const int ox = e % RO, oy = e / RO;
-        const uint32_t c = wrap_add(gx0, ox, M) + M * wrap_add(gy0, oy, M);
-        const uint32_t m = v.cnt_in[c];
-        const float4 px = *reinterpret_cast<const float4 *>(v.x_in + (size_t)c * 4);
-        const float4 py = *reinterpret_cast<const float4 *>(v.y_in + (size_t)c * 4);
-        uint32_t g = 0;
+    // ---- load the region ----------------------------------------------------
+    // Counts and slot 0 (most cells hold one disk) are loaded together, the
+    // other slots where the count asks for them.
+    if (tid == 0) L.big = 0u;
+    uint32_t m_r[NIT], c_r[NIT];
+    float4 px_r[NIT], py_r[NIT];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint32_t cls = (uint32_t)(comp4(px, s) < sx) | ((uint32_t)(comp4(py, s) < sy) << 1);
-            g += ((uint32_t)s < m) ? (1u << (3 * cls)) : 0u;
-        }
-        L.gcnt[e] = (uint16_t)g;
-        if (e < R * R) {
-            L.x[e] = far4;
-            L.y[e] = far4;
-        }
+    for (int i = 0; i < NIT; ++i) {
+        const int e = tid + i * THREADS;
+        const int ee = e < NL ? e : 0;
+        const uint32_t c = wrap_add(gx0, ee % RL, M) + M * wrap_add(gy0, ee / RL, M);
+        c_r[i] = c;
+        const uint32_t m = v.cnt_in[c];
+        m_r[i] = e < NL ? m : 0u;
+        px_r[i] = make_float4(v.x_in[c], kFar, kFar, kFar);
+        py_r[i] = make_float4(v.y_in[c], kFar, kFar, kFar);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < RO * RO; e += THREADS) {
-        const int ox = e % RO, oy = e / RO;
-        const uint32_t c = wrap_add(gx0, ox, M) + M * wrap_add(gy0, oy, M);
-        const uint32_t m = v.cnt_in[c];
-        const float4 px = *reinterpret_cast<const float4 *>(v.x_in + (size_t)c * 4);
-        const float4 py = *reinterpret_cast<const float4 *>(v.y_in + (size_t)c * 4);
-        const bool own_src = ox >= kHalo - 1 && ox <= kHalo + own_x && oy >= kHalo - 1 &&
-                             oy <= kHalo + own_y;
-        const uint4 tg = own_src ? *reinterpret_cast<const uint4 *>(v.tag_in + (size_t)c * 4)
-                                 : make_uint4(0, 0, 0, 0);
-        // class counts of the old cells before this one in each destination
-        const int oxm = ox > 0 ? ox - 1 : 0, oym = oy > 0 ? oy - 1 : 0;
-        const int oxp = ox < R ? ox + 1 : R;
-        const uint32_t g_l = L.gcnt[oxm + RO * oy];    // (ox-1, oy)
-        const uint32_t g_d = L.gcnt[ox + RO * oym];    // (ox, oy-1)
-        const uint32_t g_dr = L.gcnt[oxp + RO * oym];  // (ox+1, oy-1)
-        const uint32_t g_dl = L.gcnt[oxm + RO * oym];  // (ox-1, oy-1)
-        const uint32_t g_me = L.gcnt[e];
-        // base slot of each class in its destination, 8 bits per class
-        const uint32_t b1 = g_l & 7u;
-        const uint32_t b2 = (g_d & 7u) + ((g_dr >> 3) & 7u);
-        const uint32_t b3 = (g_dl & 7u) + ((g_d >> 3) & 7u) + ((g_l >> 6) & 7u);
-        const uint32_t bases = (b1 << 8) | (b2 << 16) | (b3 << 24);
-        // destination of each class: (ox - wx, oy - wy), inside the region?
-        const bool in0 = ox < R && oy < R, in1 = ox >= 1 && oy < R;
-        const bool in2 = ox < R && oy >= 1, in3 = ox >= 1 && oy >= 1;
-        const uint32_t ok = (uint32_t)in0 | ((uint32_t)in1 << 1) | ((uint32_t)in2 << 2) |
-                            ((uint32_t)in3 << 3);
-        const int d0 = pidx<R>(ox, oy), d1 = pidx<R>(ox - 1, oy);
-        const int d2 = pidx<R>(ox, oy - 1), d3 = pidx<R>(ox - 1, oy - 1);
-        // own-block destinations get their tags written here
-        const int ex = ox - kHalo, ey = oy - kHalo;
-        uint32_t seen = 0;  // 3-bit counters per class within this old cell
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const float xs = comp4(px, s), ys = comp4(py, s);
-            const uint32_t wx = xs < sx, wy = ys < sy, cls = wx | (wy << 1);
-            const uint32_t slot = ((bases >> (8 * cls)) & 0xFFu) + ((seen >> (3 * cls)) & 7u);
-            seen += 1u << (3 * cls);
-            const bool go = (uint32_t)s < m && ((ok >> cls) & 1u) && slot < 4;
-            if (!go) continue;
-            const int dst = cls == 0 ? d0 : cls == 1 ? d1 : cls == 2 ? d2 : d3;
-            const float u = ((xs - sx) + (wx ? w : 0.0f)) - cen;
-            const float t = ((ys - sy) + (wy ? w : 0.0f)) - cen;
-            reinterpret_cast<float *>(&L.x[dst])[slot] = u;
-            reinterpret_cast<float *>(&L.y[dst])[slot] = t;
-            const int dxo = ex - (int)wx, dyo = ey - (int)wy;
-            if (dxo >= 0 && dxo < own_x && dyo >= 0 && dyo < own_y) {
-                const size_t oc = (size_t)(I0 + dxo) + (size_t)M * (J0 + dyo);
-                v.tag_out[oc * 4 + slot] = compu4(tg, s);
+    for (int i = 0; i < NIT; ++i) {
+        const uint32_t c = c_r[i], m = m_r[i];
+        if (m > 1) {
+            px_r[i].y = v.x_in[NC + c];
+            py_r[i].y = v.y_in[NC + c];
+            if (m > 2) {
+                px_r[i].z = v.x_in[2 * NC + c];
+                py_r[i].z = v.y_in[2 * NC + c];
+                if (m > 3) {
+                    px_r[i].w = v.x_in[3 * NC + c];
+                    py_r[i].w = v.y_in[3 * NC + c];
+                }
             }
         }
-        if (in0) {  // the count of new cell (ox, oy)
-            const uint32_t g_r = L.gcnt[oxp + RO * oy];        // (ox+1, oy)
-            const uint32_t g_u = L.gcnt[ox + RO * (oy + 1)];   // (ox, oy+1)
-            const uint32_t g_ur = L.gcnt[oxp + RO * (oy + 1)]; // (ox+1, oy+1)
-            const uint32_t n = (g_me & 7u) + ((g_r >> 3) & 7u) + ((g_u >> 6) & 7u) +
-                               ((g_ur >> 9) & 7u);
-            if (n > 4) atomicOr(&v.dev->overflow, 1u);
-            const uint32_t nc = n > 4 ? 4 : n;
-            L.cnt[d0] = (uint8_t)nc;
-            if (ex >= 0 && ex < own_x && ey >= 0 && ey < own_y)
-                v.cnt_out[(size_t)(I0 + ex) + (size_t)M * (J0 + ey)] = (uint8_t)nc;
-        }
+    }
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int e = tid + i * THREADS;
+        if (e >= NL) break;
+        const uint32_t m = m_r[i];
+        const int li = pidx<R>(e % RL, e / RL);
+        float4 sx4 = px_r[i], sy4 = py_r[i];
+        sx4.x = m > 0 ? sx4.x - cen : kFar;
+        sy4.x = m > 0 ? sy4.x - cen : kFar;
+        sx4.y = m > 1 ? sx4.y - cen : kFar;
+        sy4.y = m > 1 ? sy4.y - cen : kFar;
+        sx4.z = m > 2 ? sx4.z - cen : kFar;
+        sy4.z = m > 2 ? sy4.z - cen : kFar;
+        sx4.w = m > 3 ? sx4.w - cen : kFar;
+        sy4.w = m > 3 ? sy4.w - cen : kFar;
+        L.x[li] = sx4;
+        L.y[li] = sy4;
+        L.cnt[li] = (uint8_t)m;
+        if (m > 2) L.big = 1u;
     }
     __syncthreads();
+
+    // Tags of the extended block, loaded now and held in registers through
+    // the passes: a disk keeps its slot while the passes move it.
+    uint4 tg_r[NEIT];
+#pragma unroll
+    for (int i = 0; i < NEIT; ++i) {
+        const int f = tid + i * THREADS;
+        const int ex = f % TE, ey = f / TE;
+        tg_r[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (f < NE && ex <= own_x && ey <= own_y) {
+            const uint32_t m = L.cnt[pidx<R>(ex + kHalo, ey + kHalo)];
+            const uint32_t c = wrap_add(I0, ex, M) + M * wrap_add(J0, ey, M);
+            if (m > 0) tg_r[i].x = v.tag_in[c];
+            if (m > 1) tg_r[i].y = v.tag_in[NC + c];
+            if (m > 2) tg_r[i].z = v.tag_in[2 * NC + c];
+            if (m > 3) tg_r[i].w = v.tag_in[3 * NC + c];
+        }
+    }
 
     // ---- four colour sub-sweeps --------------------------------------------
     PassCtx ctx;
@@ -307,41 +366,128 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const BoxView &v, uint3
     ctx.own_x = own_x;
     ctx.own_y = own_y;
     ctx.cen = cen;
+    ctx.big = __builtin_amdgcn_readfirstlane(L.big) != 0u;
+    // I0 and J0 are even, so the colour parity in region coordinates equals
+    // the global one
+    uint32_t col[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) col[p] = colour_of_pass(d.perm, p);
+    int total[4];
+    compact_passes<TILE, THREADS>(L, tid, col, total);
     uint32_t trials = 0, accepts = 0;
     for (int p = 0; p < 4; ++p) {
-        // I0 and J0 are even, so the colour parity in region coordinates
-        // equals the global one; each colour has its own instantiation with
-        // compile-time neighbour offsets
-        switch (colour_of_pass(d.perm, p)) {
-        case 0: run_pass<TILE, THREADS, 0, 0>(L, v, ctx, p, trials, accepts); break;
-        case 1: run_pass<TILE, THREADS, 1, 0>(L, v, ctx, p, trials, accepts); break;
-        case 2: run_pass<TILE, THREADS, 0, 1>(L, v, ctx, p, trials, accepts); break;
-        default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, p, trials, accepts); break;
+        // each colour has its own instantiation with compile-time neighbour
+        // offsets
+        switch (col[p]) {
+        case 0: run_pass<TILE, THREADS, 0, 0>(L, v, ctx, tid, p, total[p], trials, accepts); break;
+        case 1: run_pass<TILE, THREADS, 1, 0>(L, v, ctx, tid, p, total[p], trials, accepts); break;
+        case 2: run_pass<TILE, THREADS, 0, 1>(L, v, ctx, tid, p, total[p], trials, accepts); break;
+        default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, tid, p, total[p], trials, accepts); break;
         }
         __syncthreads();
     }
 
-    // ---- write the own block's offsets back (cell-local, slots >= n as 0) ---
-    for (int e = threadIdx.x; e < TILE * TILE; e += THREADS) {
-        const int ox = e % TILE, oy = e / TILE;
-        if (ox >= own_x || oy >= own_y) continue;
-        const int li = pidx<R>(ox + kHalo, oy + kHalo);
-        const uint32_t n = L.cnt[li];
-        const float4 sx4 = L.x[li], sy4 = L.y[li];
+    // ---- canonical state of the own block; wrap classes for the next grid ---
+    // Old cell (ex, ey) of the extended block sends its disks to new cell
+    // (ex - wx, ey - wy) of the next sweep's grid, shifted by s'.
+    const SweepDraws dn = sweep_draws(v.seed_lo, v.seed_hi, sweep + 1, v.W);
+    const float sxn = (float)dn.kx * kQ, syn = (float)dn.ky * kQ;
+    float4 ux_r[NEIT], uy_r[NEIT];
+    uint32_t me_r[NEIT];
+#pragma unroll
+    for (int i = 0; i < NEIT; ++i) {
+        const int f = tid + i * THREADS;
+        const int ex = f % TE, ey = f / TE;
+        const bool in_ext = f < NE && ex <= own_x && ey <= own_y;
+        const int li = pidx<R>(ex + kHalo, ey + kHalo);
+        const uint32_t m = in_ext ? L.cnt[li] : 0u;
+        const float4 sx4 = L.x[in_ext ? li : 0], sy4 = L.y[in_ext ? li : 0];
         float4 ux, uy;
-        ux.x = n > 0 ? sx4.x + cen : 0.0f;
-        ux.y = n > 1 ? sx4.y + cen : 0.0f;
-        ux.z = n > 2 ? sx4.z + cen : 0.0f;
-        ux.w = n > 3 ? sx4.w + cen : 0.0f;
-        uy.x = n > 0 ? sy4.x + cen : 0.0f;
-        uy.y = n > 1 ? sy4.y + cen : 0.0f;
-        uy.z = n > 2 ? sy4.z + cen : 0.0f;
-        uy.w = n > 3 ? sy4.w + cen : 0.0f;
-        const size_t c = (size_t)(I0 + ox) + (size_t)M * (J0 + oy);
-        *reinterpret_cast<float4 *>(v.x_out + c * 4) = ux;
-        *reinterpret_cast<float4 *>(v.y_out + c * 4) = uy;
+        ux.x = sx4.x + cen;
+        ux.y = sx4.y + cen;
+        ux.z = sx4.z + cen;
+        ux.w = sx4.w + cen;
+        uy.x = sy4.x + cen;
+        uy.y = sy4.y + cen;
+        uy.z = sy4.z + cen;
+        uy.w = sy4.w + cen;
+        me_r[i] = m;
+        ux_r[i] = ux;
+        uy_r[i] = uy;
+        if (in_ext && ex < own_x && ey < own_y && v.cnt_can) {
+            const uint32_t c = (I0 + ex) + M * (J0 + ey);
+            v.cnt_can[c] = (uint8_t)m;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                if ((uint32_t)s < m) {
+                    v.x_can[s * NC + c] = comp4(ux, s);
+                    v.y_can[s * NC + c] = comp4(uy, s);
+                    v.tag_can[s * NC + c] = s == 0 ? tg_r[i].x : s == 1 ? tg_r[i].y
+                                          : s == 2 ? tg_r[i].z : tg_r[i].w;
+                }
+            }
+        }
+        uint32_t g = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint32_t cls = (uint32_t)(comp4(ux, s) < sxn) | ((uint32_t)(comp4(uy, s) < syn) << 1);
+            g += ((uint32_t)s < m) ? (1u << (3 * cls)) : 0u;
+        }
+        if (f < NE) L.gcnt[f] = (uint16_t)g;
     }
-    count_trials(v.dev, trials, accepts);
+    __syncthreads();
+
+    // ---- scatter into the next sweep's cell lists ---------------------------
+    // New cell (I, J) takes the disks of old (I, J) that do not wrap, then
+    // those of (I+1, J) wrapping in x only, (I, J+1) in y only, (I+1, J+1) in
+    // both, each in old slot order.  A disk's slot follows from the class
+    // counts of the old cells before its own in that order.
+#pragma unroll
+    for (int i = 0; i < NEIT; ++i) {
+        const int f = tid + i * THREADS;
+        const int ex = f % TE, ey = f / TE;
+        if (f >= NE || ex > own_x || ey > own_y) continue;
+        const uint32_t m = me_r[i];
+        const float4 ux = ux_r[i], uy = uy_r[i];
+        const uint4 tg = tg_r[i];
+        const int exm = ex > 0 ? ex - 1 : 0, eym = ey > 0 ? ey - 1 : 0;
+        const int exp1 = ex < TE - 1 ? ex + 1 : TE - 1, eyp1 = ey < TE - 1 ? ey + 1 : TE - 1;
+        const uint32_t g_l = L.gcnt[exm + TE * ey];     // (ex-1, ey)
+        const uint32_t g_d = L.gcnt[ex + TE * eym];     // (ex, ey-1)
+        const uint32_t g_dr = L.gcnt[exp1 + TE * eym];  // (ex+1, ey-1)
+        const uint32_t g_dl = L.gcnt[exm + TE * eym];   // (ex-1, ey-1)
+        // base slot of each class in its destination, 8 bits per class
+        const uint32_t b1 = g_l & 7u;
+        const uint32_t b2 = (g_d & 7u) + ((g_dr >> 3) & 7u);
+        const uint32_t b3 = (g_dl & 7u) + ((g_d >> 3) & 7u) + ((g_l >> 6) & 7u);
+        const uint32_t bases = (b1 << 8) | (b2 << 16) | (b3 << 24);
+        uint32_t seen = 0;  // 3-bit counters per class within this old cell
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if ((uint32_t)s >= m) break;
+            const float us = comp4(ux, s), vs = comp4(uy, s);
+            const uint32_t wx = us < sxn, wy = vs < syn, cls = wx | (wy << 1);
+            const uint32_t slot = ((bases >> (8 * cls)) & 0xFFu) + ((seen >> (3 * cls)) & 7u);
+            seen += 1u << (3 * cls);
+            const int nx = ex - (int)wx, ny = ey - (int)wy;
+            if (nx < 0 || nx >= own_x || ny < 0 || ny >= own_y || slot >= 4) continue;
+            const uint32_t nc = (I0 + nx) + M * (J0 + ny);
+            v.x_out[slot * NC + nc] = (us - sxn) + (wx ? w : 0.0f);
+            v.y_out[slot * NC + nc] = (vs - syn) + (wy ? w : 0.0f);
+            v.tag_out[slot * NC + nc] = s == 0 ? tg.x : s == 1 ? tg.y : s == 2 ? tg.z : tg.w;
+        }
+        if (ex < own_x && ey < own_y) {  // the count of new cell (ex, ey)
+            const uint32_t g_me = L.gcnt[f];
+            const uint32_t g_r = L.gcnt[ex + 1 + TE * ey];         // (ex+1, ey)
+            const uint32_t g_u = L.gcnt[ex + TE * (ey + 1)];       // (ex, ey+1)
+            const uint32_t g_ur = L.gcnt[ex + 1 + TE * (ey + 1)];  // (ex+1, ey+1)
+            const uint32_t n = (g_me & 7u) + ((g_r >> 3) & 7u) + ((g_u >> 6) & 7u) +
+                               ((g_ur >> 9) & 7u);
+            if (n > 4) atomicOr((uint32_t *)&v.dev->overflow, 1u);
+            v.cnt_out[(I0 + ex) + M * (J0 + ey)] = (uint8_t)(n > 4 ? 4 : n);
+        }
+    }
+    count_trials((DevScalars *)v.dev, trials, accepts);
 }
 
 template <int TILE, int THREADS>
@@ -353,24 +499,48 @@ __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint
     // contiguous run of tiles so that shared halo cells meet in its L2.
     const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
     if (tile >= ntx * nty) return;
-    fused_tile<TILE, THREADS>(L, v, (tile % ntx) * TILE, (tile / ntx) * TILE);
+    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE);
 }
 
 // Persistent form for a batch of independent boxes: workgroups stride over
 // a work list of (box, tile) items, item = box << 20 | tile.  All boxes of a
 // batch advance in step, so one buffer parity serves them all.
 template <int TILE, int THREADS>
-__global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *views,
-                                                         const uint32_t *items, uint32_t n_items,
-                                                         uint32_t parity, uint32_t offset) {
+__global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restrict__ views,
+                                                         const uint32_t *__restrict__ items,
+                                                         uint32_t n_items, uint32_t parity,
+                                                         uint32_t offset) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const uint32_t item = items[it], box = item >> 20, tile = item & 0xFFFFFu;
-        BoxView v = views[2 * box + parity];
+        const BoxView &src = views[2 * box + parity];
+        GlobalView v;
+        v.cnt_in = (const MPMC_GLOBAL uint8_t *)src.cnt_in;
+        v.x_in = (const MPMC_GLOBAL float *)src.x_in;
+        v.y_in = (const MPMC_GLOBAL float *)src.y_in;
+        v.tag_in = (const MPMC_GLOBAL uint32_t *)src.tag_in;
+        v.cnt_out = (MPMC_GLOBAL uint8_t *)src.cnt_out;
+        v.x_out = (MPMC_GLOBAL float *)src.x_out;
+        v.y_out = (MPMC_GLOBAL float *)src.y_out;
+        v.tag_out = (MPMC_GLOBAL uint32_t *)src.tag_out;
+        v.cnt_can = (MPMC_GLOBAL uint8_t *)src.cnt_can;
+        v.x_can = (MPMC_GLOBAL float *)src.x_can;
+        v.y_can = (MPMC_GLOBAL float *)src.y_can;
+        v.tag_can = (MPMC_GLOBAL uint32_t *)src.tag_can;
+        v.dev = (MPMC_GLOBAL DevScalars *)src.dev;
+        v.M = src.M;
+        v.W = src.W;
+        v.cap = src.cap;
+        v.CS = src.CS;
+        v.step_m = src.step_m;
+        v.n_trial = src.n_trial;
+        v.w = src.w;
+        v.seed_lo = src.seed_lo;
+        v.seed_hi = src.seed_hi;
         v.offset = offset;
         const uint32_t ntx = (v.M + TILE - 1) / TILE;
-        fused_tile<TILE, THREADS>(L, v, (tile % ntx) * TILE, (tile / ntx) * TILE);
+        fused_tile<TILE, THREADS>(L, v, opaque_tid(), (tile % ntx) * TILE, (tile / ntx) * TILE);
         __syncthreads();
     }
 }
@@ -437,9 +607,9 @@ const FusedShape *fused_shapes(uint32_t *count) {
 
 bool fused_supported(const BoxView &v, const FusedShape &s) {
     if (v.CS != 4 || v.cap > 4) return false;
-    // the halo region must not wrap onto itself: every index below is
-    // reduced modulo M with a single conditional subtraction
-    if (s.tile + 2 * kHalo > v.M || (s.tile & 1u)) return false;
+    // the loaded region (tile + 9 cells a side) must not wrap onto itself:
+    // every index is reduced modulo M with a single conditional subtraction
+    if (s.tile + 2 * kHalo + 2 > v.M || (s.tile & 1u)) return false;
     for (const Entry &e : kShapes)
         if (e.tile == s.tile && e.threads == s.threads) return true;
     return false;

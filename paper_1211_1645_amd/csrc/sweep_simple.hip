@@ -1,8 +1,9 @@
-// sweep_simple.hip — the straightforward schedule of one MPMC sweep: a re-bin
-// kernel for the shifted grid, then one kernel per colour sub-sweep with one
-// thread per active cell reading its 3 x 3 neighbourhood from global memory
-// (Sec. II.B).  It is the baseline the fused tile kernel is checked against
-// and the fallback for boxes too small to tile.
+// sweep_simple.hip — the straightforward schedule of one MPMC sweep (Sec.
+// II.B): one kernel per colour sub-sweep with one thread per active cell
+// reading its 3 x 3 neighbourhood from global memory, on cell lists already
+// binned in the sweep's shifted grid, then a re-bin kernel into the next
+// sweep's grid.  It is the baseline the fused tile kernel is checked
+// against and the fallback for boxes too small to tile.
 #include "mpmc_kernels.hpp"
 
 namespace mpmc {
@@ -19,6 +20,7 @@ __global__ void __launch_bounds__(256) k_rebin(BoxView v) {
     const uint64_t sweep = v.dev->sweep + v.offset;
     const SweepDraws d = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
     const float sx = (float)d.kx * kQ, sy = (float)d.ky * kQ;
+    const uint32_t NC = M * M;
     uint32_t n = 0;
     for (uint32_t src = 0; src < 4; ++src) {
         const uint32_t di = src & 1u, dj = src >> 1;
@@ -27,17 +29,17 @@ __global__ void __launch_bounds__(256) k_rebin(BoxView v) {
         const uint32_t c = i + M * j;
         const uint32_t m = v.cnt_in[c];
         for (uint32_t s = 0; s < m; ++s) {
-            float u = v.x_in[c * v.CS + s] - sx;
-            float w = v.y_in[c * v.CS + s] - sy;
+            float u = v.x_in[slot_at(c, s, NC)] - sx;
+            float w = v.y_in[slot_at(c, s, NC)] - sy;
             const uint32_t wx = u < 0.0f, wy = w < 0.0f;
             if (wx != di || wy != dj) continue;
             if (wx) u += v.w;
             if (wy) w += v.w;
             if (n < v.cap) {
-                const uint32_t o = idx * v.CS + n;
+                const uint32_t o = slot_at(idx, n, NC);
                 v.x_out[o] = u;
                 v.y_out[o] = w;
-                v.tag_out[o] = v.tag_in[c * v.CS + s];
+                v.tag_out[o] = v.tag_in[slot_at(c, s, NC)];
                 ++n;
             } else {
                 atomicOr(&v.dev->overflow, 1u);
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(256) k_pass(BoxView v, uint32_t pass) {
             for (uint32_t tr = 0; tr < v.n_trial; ++tr) {
                 const Words w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
                 const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : perm[tr % n];
-                const uint32_t k = cell * v.CS + slot;
+                const uint32_t k = slot_at(cell, slot, M * M);
                 const float xn = v.x_out[k] + step_from_word(w4.w1, v.step_m);
                 const float yn = v.y_out[k] + step_from_word(w4.w2, v.step_m);
                 ++trials;
@@ -96,8 +98,8 @@ __global__ void __launch_bounds__(256) k_pass(BoxView v, uint32_t pass) {
                         const uint32_t m = v.cnt_out[nb];
                         for (uint32_t s = 0; s < m; ++s) {
                             if (nb == cell && s == slot) continue;
-                            const float dx = (v.x_out[nb * v.CS + s] - xn) + cwx;
-                            const float dy = (v.y_out[nb * v.CS + s] - yn) + cwy;
+                            const float dx = (v.x_out[slot_at(nb, s, M * M)] - xn) + cwx;
+                            const float dy = (v.y_out[slot_at(nb, s, M * M)] - yn) + cwy;
                             if (overlap_f32(dx, dy)) { bad = true; break; }
                         }
                     }
@@ -158,16 +160,29 @@ void launch_advance_batch(const AdvanceDesc *desc, uint32_t nbox, uint32_t count
     k_advance_batch<<<(nbox + 63) / 64, 64, 0, st>>>(desc, nbox, count);
 }
 
-void launch_simple_sweep(const BoxView &v, hipStream_t st) {
-    const uint32_t nc = v.M * v.M;
-    k_rebin<<<(nc + 255) / 256, 256, 0, st>>>(v);
-    const uint32_t na = (v.M / 2) * (v.M / 2);
-    for (uint32_t p = 0; p < 4; ++p) k_pass<<<(na + 255) / 256, 256, 0, st>>>(v, p);
+BoxView in_place(const BoxView &v) {
+    BoxView p = v;
+    p.cnt_out = const_cast<uint8_t *>(v.cnt_in);
+    p.x_out = const_cast<float *>(v.x_in);
+    p.y_out = const_cast<float *>(v.y_in);
+    p.tag_out = const_cast<uint32_t *>(v.tag_in);
+    return p;
 }
 
-void launch_simple_sweep_rebin_only(const BoxView &v, hipStream_t st) {
+void launch_rebin(const BoxView &v, hipStream_t st) {
     const uint32_t nc = v.M * v.M;
     k_rebin<<<(nc + 255) / 256, 256, 0, st>>>(v);
+}
+
+// The four passes on the input lists in place (they become the canonical
+// state), then the re-bin into the next sweep's grid.
+void launch_simple_sweep(const BoxView &v, hipStream_t st) {
+    const BoxView pv = in_place(v);
+    const uint32_t na = (v.M / 2) * (v.M / 2);
+    for (uint32_t p = 0; p < 4; ++p) k_pass<<<(na + 255) / 256, 256, 0, st>>>(pv, p);
+    BoxView rv = v;
+    rv.offset = v.offset + 1;
+    launch_rebin(rv, st);
 }
 
 void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_t W,

@@ -67,6 +67,27 @@ def test_shuffled_trials_bit_exact(gpu_lib, n_trial):
         assert_same_state(g, o)
 
 
+SPARSE = dict(N=64 * 64, eta=0.35, seed=3, lattice=0, step_m=200)
+
+
+@pytest.mark.parametrize("tile,threads", [(8, 64), (24, 256)])
+def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
+    """Cells 2.8 sigma wide in a dilute box hold three disks now and then:
+    the fused kernel tests slots 2 and 3 only in tiles that hold such a
+    cell, and both forms must give the oracle's trajectory."""
+    g = gpu_box(gpu_lib, **SPARSE, cell_min=2.8, schedule="simple")
+    g.set_schedule("fused", tile, threads)
+    o = OracleBox(**SPARSE, cell_min=2.8)
+    done = 0
+    for k in (10, 100):
+        g.sweep(k - done)
+        o.sweep(k - done)
+        done = k
+        assert_same_state(g, o)
+    assert (g.cells()[0] >= 3).sum() > 0
+    assert g.validate() == (0, 0)
+
+
 def test_config2_trajectory_bit_exact(gpu_lib):
     g = gpu_box(gpu_lib, **CONFIG2)  # autotuned fused schedule
     assert g.info()["schedule"] == 2
