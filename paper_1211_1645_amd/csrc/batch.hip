@@ -26,8 +26,7 @@ struct Batch {
     mpmc_params p{};
     hipStream_t stream = nullptr, cap_stream = nullptr;
     BoxView *d_views = nullptr;    // per box and buffer parity
-    BoxView *d_views_t = nullptr;  // the same without canonical output, for timing
-    bool timing = false;
+    BoxView *d_views_t = nullptr;  // the same without canonical output
     uint32_t *d_items = nullptr;
     AdvanceDesc *d_adv = nullptr;
     uint32_t n_items = 0;
@@ -57,10 +56,11 @@ struct Batch {
         boxes.clear();
     }
 
-    // one sweep of every box reading buffer `from`
-    void launch(int from, uint32_t offset, hipStream_t st) {
+    // one sweep of every box reading buffer `from`; `canon`: also write the
+    // canonical state (the last sweep of a run)
+    void launch(int from, uint32_t offset, hipStream_t st, bool canon) {
         if (fused) {
-            launch_fused_batch(timing ? d_views_t : d_views, d_items, n_items, (uint32_t)from, offset,
+            launch_fused_batch(canon ? d_views : d_views_t, d_items, n_items, (uint32_t)from, offset,
                                shape, st);
         } else {
             for (Box *b : boxes) {
@@ -96,7 +96,8 @@ struct Batch {
         graph = nullptr;
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-        for (uint32_t k = 0; k < graph_sweeps; ++k) launch((int)(k & 1u), k, cap_stream);
+        for (uint32_t k = 0; k < graph_sweeps; ++k)
+            launch((int)(k & 1u), k, cap_stream, k + 1 == graph_sweeps);
         launch_advance_batch(d_adv, (uint32_t)boxes.size(), graph_sweeps, cap_stream);
         HIPCHK(hipStreamEndCapture(cap_stream, &g));
         hipError_t e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
@@ -122,7 +123,7 @@ struct Batch {
                 k -= graph_sweeps;
                 continue;
             }
-            launch(cur, 0, stream);
+            launch(cur, 0, stream, k == 1);
             launch_advance_batch(d_adv, (uint32_t)boxes.size(), 1, stream);
             HIPCHK(hipGetLastError());
             cur ^= 1;
@@ -161,12 +162,10 @@ struct Batch {
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
-        timing = true;
-        for (int r = 0; r < 2; ++r) launch(cur, 0, stream);
+        for (int r = 0; r < 2; ++r) launch(cur, 0, stream, false);
         (void)hipEventRecord(e0, stream);
-        for (int r = 0; r < 6; ++r) launch(cur, 0, stream);
+        for (int r = 0; r < 6; ++r) launch(cur, 0, stream, false);
         (void)hipEventRecord(e1, stream);
-        timing = false;
         hipError_t e = hipEventSynchronize(e1);
         float t = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);

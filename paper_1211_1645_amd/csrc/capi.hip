@@ -167,8 +167,8 @@ int Box::read_scalars() {
     HIPCHK(hipStreamSynchronize(stream));
     host.trials = host.accepts = 0;
     for (int s = 0; s < kCountSlots; ++s) {
-        host.trials += host.slot_trials[s];
-        host.accepts += host.slot_accepts[s];
+        host.trials += host.slots[s].trials;
+        host.accepts += host.slots[s].accepts;
     }
     if (host.overflow) return fail(MPMC_EOVERFLOW, "a cell exceeded its capacity");
     return MPMC_OK;
@@ -346,9 +346,14 @@ int mpmc::create_box(Box **out, uint32_t N, double eta, uint64_t seed, const mpm
 
 // ---------------------------------------------------------------------------
 // sweeps
-int Box::launch_one(int from, uint32_t offset, hipStream_t st) {
+int Box::launch_one(int from, uint32_t offset, hipStream_t st, bool canon) {
     BoxView v = view(from);
     v.offset = offset;
+    if (!canon) {  // only the last sweep of a run leaves the canonical state
+        v.cnt_can = nullptr;
+        v.x_can = v.y_can = nullptr;
+        v.tag_can = nullptr;
+    }
     if (sched == MPMC_SCHED_SIMPLE) launch_simple_sweep(v, st);
     else launch_fused_sweep(v, shape, st);
     return MPMC_OK;
@@ -361,7 +366,8 @@ int Box::build_graph() {
     }
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-    for (uint32_t k = 0; k < graph_sweeps; ++k) launch_one((int)(k & 1u), k, cap_stream);
+    for (uint32_t k = 0; k < graph_sweeps; ++k)
+        launch_one((int)(k & 1u), k, cap_stream, k + 1 == graph_sweeps);
     launch_advance(dev, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)g.W, g.Lq,
                    graph_sweeps, cap_stream);
     HIPCHK(hipStreamEndCapture(cap_stream, &graph));
@@ -394,7 +400,7 @@ int Box::run_sweeps(uint64_t k) {
             canon_in_c = sched != MPMC_SCHED_SIMPLE;
             continue;
         }
-        launch_one(cur, 0, stream);
+        launch_one(cur, 0, stream, k == 1);
         launch_advance(dev, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)g.W, g.Lq, 1, stream);
         HIPCHK(hipGetLastError());
         cur ^= 1;

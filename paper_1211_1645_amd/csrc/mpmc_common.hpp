@@ -104,7 +104,10 @@ __device__ __forceinline__ float r2_f32(float dx, float dy) {
 }
 
 // Device-resident scalars of one box.
-constexpr int kCountSlots = 64;
+constexpr int kCountSlots = 1024;
+struct CountSlot {
+    unsigned long long trials, accepts;
+};
 
 struct DevScalars {
     unsigned long long sweep;     // sweeps completed
@@ -115,10 +118,9 @@ struct DevScalars {
     unsigned int error;           // a kernel-side check failed
     double psi_re, psi_im;        // global psi sum (measurement scratch)
     unsigned long long bad, overlaps;  // validate results
-    // Trial and acceptance counts, spread over slots (workgroup b adds to
-    // slot b mod 64) so that no single address takes every atomic.
-    unsigned long long slot_trials[kCountSlots];
-    unsigned long long slot_accepts[kCountSlots];
+    // Trial and acceptance counts, spread over slots (one per workgroup and
+    // wave, modulo kCountSlots) so that atomics rarely meet on one address.
+    CountSlot slots[kCountSlots];
 };
 
 // Cell lists are stored slot-major: slot s of cell c is element s * NC + c

@@ -86,7 +86,8 @@ struct Box {
     int read_scalars();
     int upload(const std::vector<uint8_t> &hc, const std::vector<uint32_t> &ht,
                const std::vector<float> &hx, const std::vector<float> &hy, const DevScalars &s);
-    int launch_one(int from, uint32_t offset, hipStream_t st);
+    // one sweep reading P[from]; `canon`: also write the canonical state
+    int launch_one(int from, uint32_t offset, hipStream_t st, bool canon);
     int build_graph();
     uint64_t key() const;
     int run_sweeps(uint64_t k);

@@ -8,24 +8,23 @@ namespace mpmc {
 // reduction, one LDS atomic per wave, then one 64-bit global atomic per
 // workgroup into slot (blockIdx mod 64).  Every thread of the workgroup must
 // call it (it contains barriers).
+// Sum over the wave of a small per-lane count, one bit plane per ballot.
+__device__ __forceinline__ uint32_t wave_sum_bits(uint32_t v) {
+    uint32_t s = 0;
+    for (int b = 0; b < 32 && __ballot((v >> b) != 0u) != 0ull; ++b)
+        s += (uint32_t)__popcll(__ballot((v >> b) & 1u)) << b;
+    return s;
+}
+
+// Adds the wave's trial and acceptance counts (per lane t, a) to the box
+// totals: lane 0 adds the wave sums to one count slot, chosen by workgroup
+// and wave.  Every lane of the wave must call it; no barrier is involved.
 __device__ __forceinline__ void count_trials(DevScalars *dev, uint32_t t, uint32_t a) {
-    __shared__ uint32_t red[2];
-    if (threadIdx.x == 0) { red[0] = 0; red[1] = 0; }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        t += __shfl_xor(t, off, 64);
-        a += __shfl_xor(a, off, 64);
-    }
-    __syncthreads();
-    if ((threadIdx.x & 63u) == 0 && t != 0) {
-        atomicAdd(&red[0], t);
-        atomicAdd(&red[1], a);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && red[0] != 0) {
-        const uint32_t s = blockIdx.x % kCountSlots;
-        atomicAdd(&dev->slot_trials[s], (unsigned long long)red[0]);
-        atomicAdd(&dev->slot_accepts[s], (unsigned long long)red[1]);
+    const uint32_t st = wave_sum_bits(t), sa = wave_sum_bits(a);
+    if ((threadIdx.x & 63u) == 0 && st != 0) {
+        const uint32_t s = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCountSlots;
+        atomicAdd(&dev->slots[s].trials, (unsigned long long)st);
+        atomicAdd(&dev->slots[s].accepts, (unsigned long long)sa);
     }
 }
 
