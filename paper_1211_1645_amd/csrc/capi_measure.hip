@@ -63,6 +63,11 @@ int mpmc::lsq_poly(const std::vector<double> &t, const std::vector<double> &yv, 
     return 0;
 }
 
+int Box::measure_work() {
+    if (meas_work) return MPMC_OK;
+    return alloc_dev(&meas_work, measure_work_bytes(p.hist_bins));
+}
+
 int Box::locate() {
     if (!loc) {
         int rc = alloc_dev((void **)&loc, (size_t)N * 4);
@@ -104,9 +109,13 @@ extern "C" int mpmc_accumulate_contacts(mpmc_box bh) {
     const uint32_t K = b->p.hist_bins;
     const double rmax = 2.0 + K * b->p.hist_dr;
     const uint32_t h = ((double)b->g.w >= rmax) ? 1u : 2u;
-    int lrc = b->locate();
-    if (lrc) return lrc;
-    launch_contact_hist(b->mview(), b->edges, K, h, b->hist, nullptr, b->loc, b->stream);
+    if (!measure_tiled(b->mview(), h)) {
+        int lrc = b->locate();
+        if (lrc) return lrc;
+    }
+    int wrc = b->measure_work();
+    if (wrc) return wrc;
+    launch_contact_hist(b->mview(), b->edges, K, h, b->hist, nullptr, b->loc, b->meas_work, b->stream);
     HIPCHK(hipGetLastError());
     ++b->n_conf;
     if (b->p.hist_block > 0 && b->n_conf - b->block_conf0 == b->p.hist_block) {
@@ -187,10 +196,14 @@ extern "C" int mpmc_contact_hist_subset(mpmc_box bh, const uint8_t *sel, int64_t
     HIPCHK(hipMemcpyAsync(dsel, sel, b->N, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemsetAsync(dh, 0, K * 8, b->stream));
     const double rmax = 2.0 + K * b->p.hist_dr;
-    rc = b->locate();
+    const uint32_t hs = ((double)b->g.w >= rmax) ? 1u : 2u;
+    if (!measure_tiled(b->mview(), hs)) {
+        rc = b->locate();
+        if (rc) return rc;
+    }
+    rc = b->measure_work();
     if (rc) return rc;
-    launch_contact_hist(b->mview(), b->edges, K, ((double)b->g.w >= rmax) ? 1u : 2u, dh, dsel,
-                        b->loc, b->stream);
+    launch_contact_hist(b->mview(), b->edges, K, hs, dh, dsel, b->loc, b->meas_work, b->stream);
     HIPCHK(hipGetLastError());
     std::vector<unsigned long long> h(K);
     HIPCHK(hipMemcpyAsync(h.data(), dh, K * 8, hipMemcpyDeviceToHost, b->stream));
@@ -227,12 +240,18 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
     const uint32_t hmax = (M - 2) / 2;  // 2h + 1 <= M - 1: no cell seen twice
     uint32_t h = hmax < 2 ? hmax : 2;
     if (h < 1) return fail(MPMC_EINVAL, "box too small for the neighbour search");
-    rc = b->locate();
+    rc = b->measure_work();
     if (rc) return rc;
+    bool located = false;
     for (;;) {
+        if (!measure_tiled(b->mview(), h) && !located) {
+            rc = b->locate();
+            if (rc) return rc;
+            located = true;
+        }
         HIPCHK(hipMemsetAsync(&b->dev->psi_re, 0, 16, b->stream));
         HIPCHK(hipMemsetAsync(b->scratch_u32, 0, 4, b->stream));
-        launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->loc, b->stream);
+        launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->loc, b->meas_work, b->stream);
         HIPCHK(hipGetLastError());
         uint32_t failed = 0;
         HIPCHK(hipMemcpyAsync(&failed, b->scratch_u32, 4, hipMemcpyDeviceToHost, b->stream));

@@ -67,6 +67,126 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
         if (bins[k]) atomicAdd(&hist[k], (unsigned long long)bins[k]);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled forms for boxes of at most 4 slots per cell: a workgroup of 256
+// threads owns a 16 x 16 block of cells, stages the block plus a halo of h
+// cells (count, offsets and tags of every slot in use) in LDS once, and each
+// thread then serves the disks of one cell from LDS.  Neighbouring disks
+// are read from the staged copy instead of being gathered from global
+// memory once per disk.
+constexpr int kPT = 16, kStageHalo = 3, kSR = kPT + 2 * kStageHalo;
+
+struct Stage {
+    float4 x[kSR * kSR], y[kSR * kSR];
+    uint4 tag[kSR * kSR];
+    uint8_t cnt[kSR * kSR];
+};
+
+__device__ __forceinline__ float comp4f(const float4 &v, uint32_t s) {
+    return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+__device__ __forceinline__ uint32_t comp4u(const uint4 &v, uint32_t s) {
+    return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
+// Stages block (I0, J0) with halo h; region cell (rx, ry) is index rx + sr ry,
+// sr = 16 + 2 h.
+__device__ void stage_block(Stage &S, const MeasureView &m, int h, uint32_t I0, uint32_t J0) {
+    const int sr = kPT + 2 * h;
+    const uint32_t M = m.M, NC = M * M;
+    for (int e = threadIdx.x; e < sr * sr; e += blockDim.x) {
+        const int rx = e % sr, ry = e / sr;
+        const uint32_t c = wrapc((int)I0 - h + rx, M) + M * wrapc((int)J0 - h + ry, M);
+        uint32_t n = m.cnt[c];
+        n = n > 4 ? 4 : n;
+        float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), y4 = x4;
+        uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
+        if (n > 0) { x4.x = m.x[c]; y4.x = m.y[c]; t4.x = m.tag[c]; }
+        if (n > 1) { x4.y = m.x[NC + c]; y4.y = m.y[NC + c]; t4.y = m.tag[NC + c]; }
+        if (n > 2) { x4.z = m.x[2 * NC + c]; y4.z = m.y[2 * NC + c]; t4.z = m.tag[2 * NC + c]; }
+        if (n > 3) { x4.w = m.x[3 * NC + c]; y4.w = m.y[3 * NC + c]; t4.w = m.tag[3 * NC + c]; }
+        S.x[e] = x4;
+        S.y[e] = y4;
+        S.tag[e] = t4;
+        S.cnt[e] = (uint8_t)n;
+    }
+    __syncthreads();
+}
+
+// The tiled kernels run a persistent grid of at most kMeasGrid workgroups
+// over the 16 x 16 blocks and leave one partial result per workgroup, which
+// a second kernel sums: no two workgroups ever add to the same address.
+constexpr uint32_t kMeasGrid = 1024;
+
+__global__ void __launch_bounds__(256) k_contact_hist_tile(MeasureView m, const float *__restrict__ E,
+                                                           uint32_t K, int h, const uint8_t *sel,
+                                                           uint32_t *rows) {
+    __shared__ Stage S;
+    extern __shared__ uint32_t bins[];
+    for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
+    const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
+    const float e0 = E[0], eK = E[K];
+    const float rmax = sqrtf(eK) * 1.0001f + 1e-4f;  // conservative reach
+    for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
+        const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
+        stage_block(S, m, h, I0, J0);  // ends with a barrier
+        const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT, sr = kPT + 2 * h;
+        if (I0 + tx < M && J0 + ty < M) {
+            const int me = (tx + h) + sr * (ty + h);
+            const uint32_t n = S.cnt[me];
+            for (uint32_t s = 0; s < n; ++s) {
+                if (sel && !sel[comp4u(S.tag[me], s)]) continue;
+                const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
+                for (int dj = -h; dj <= h; ++dj) {
+                    // smallest |dy| to any disk of row dj: skip rows out of reach
+                    const float gy = dj > 1 ? (float)(dj - 1) * m.w + (m.w - yi)
+                                   : dj < -1 ? (float)(-dj - 1) * m.w + yi : 0.0f;
+                    if (gy > rmax) continue;
+                    for (int di = -h; di <= h; ++di) {
+                        const float gx = di > 1 ? (float)(di - 1) * m.w + (m.w - xi)
+                                       : di < -1 ? (float)(-di - 1) * m.w + xi : 0.0f;
+                        if (gx > rmax) continue;
+                        const int ne = me + di + sr * dj;
+                        const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                        const uint32_t mm = S.cnt[ne];
+                        const float4 qx = S.x[ne], qy = S.y[ne];
+                        for (uint32_t q = 0; q < mm; ++q) {
+                            if (di == 0 && dj == 0 && q == s) continue;
+                            const float dx = (comp4f(qx, q) - xi) + cwx;
+                            const float dy = (comp4f(qy, q) - yi) + cwy;
+                            const float r2 = r2_f32(dx, dy);
+                            if (!(r2 >= e0) || !(r2 < eK)) continue;
+                            // start from the square-root estimate, then settle
+                            // on the exact fp32 edges
+                            int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
+                            k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
+                            while (k > 0 && r2 < E[k]) --k;
+                            while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
+                            atomicAdd(&bins[k], 1u);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();  // S is restaged for the next block
+    }
+    for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) rows[blockIdx.x * K + k] = bins[k];
+}
+
+// hist[k] += sum over the G rows; one workgroup per bin.
+__global__ void __launch_bounds__(256) k_hist_rows_reduce(const uint32_t *rows, uint32_t G, uint32_t K,
+                                                          unsigned long long *hist) {
+    __shared__ unsigned long long part[4];
+    const uint32_t k = blockIdx.x;
+    unsigned long long s = 0;
+    for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) s += rows[g * K + k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) hist[k] += part[0] + part[1] + part[2] + part[3];
+}
+
 // Slot of every disk by tag: loc[tag] = slot_at(cell, slot, M * M).
 __global__ void __launch_bounds__(256) k_locate(MeasureView m, uint32_t *loc) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,9 +201,23 @@ void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st) {
     k_locate<<<(n + 255) / 256, 256, 0, st>>>(m, loc);
 }
 
+bool measure_tiled(const MeasureView &m, uint32_t h) {
+    return m.cap <= 4 && h <= (uint32_t)kStageHalo;
+}
+
+size_t measure_work_bytes(uint32_t K) { return (size_t)kMeasGrid * (K * 4 + sizeof(double2)); }
+
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
                          unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
-                         hipStream_t st) {
+                         void *work, hipStream_t st) {
+    if (measure_tiled(m, h)) {
+        const uint32_t nb = (m.M + kPT - 1) / kPT;
+        const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+        uint32_t *rows = static_cast<uint32_t *>(work);
+        k_contact_hist_tile<<<G, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, sel, rows);
+        k_hist_rows_reduce<<<K, 256, 0, st>>>(rows, G, K, hist);
+        return;
+    }
     k_contact_hist<<<(m.N + 255) / 256, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, hist,
                                                                           sel, loc);
 }
@@ -101,6 +235,24 @@ struct Nb6 {
 
 __device__ __forceinline__ bool nb_less(float ra, uint32_t ta, float rb, uint32_t tb) {
     return ra < rb || (ra == rb && ta < tb);
+}
+
+// psi_j of Eq. (8) from the six neighbours: mean of z^6 / |z|^6, z = dx + i dy.
+__device__ __forceinline__ void psi6_sum(const Nb6 &b, float &sr, float &si) {
+    sr = 0.0f;
+    si = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const float dx = b.dx[e], dy = b.dy[e];
+        const float ar = dx * dx - dy * dy, ai = 2.0f * dx * dy;     // z^2
+        const float br = ar * ar - ai * ai, bi = 2.0f * ar * ai;     // z^4
+        const float cr = br * ar - bi * ai, cim = br * ai + bi * ar; // z^6
+        const float r6 = b.r2[e] * b.r2[e] * b.r2[e];
+        sr += cr / r6;
+        si += cim / r6;
+    }
+    sr *= (1.0f / 6.0f);
+    si *= (1.0f / 6.0f);
 }
 
 __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, float *im,
@@ -144,18 +296,7 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
         const double reach = (double)h * (double)m.w;
         if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
         float sr = 0.0f, si = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) {
-            const float dx = b.dx[e], dy = b.dy[e];
-            const float ar = dx * dx - dy * dy, ai = 2.0f * dx * dy;     // z^2
-            const float br = ar * ar - ai * ai, bi = 2.0f * ar * ai;     // z^4
-            const float cr = br * ar - bi * ai, cim = br * ai + bi * ar; // z^6
-            const float r6 = b.r2[e] * b.r2[e] * b.r2[e];
-            sr += cr / r6;
-            si += cim / r6;
-        }
-        sr *= (1.0f / 6.0f);
-        si *= (1.0f / 6.0f);
+        psi6_sum(b, sr, si);
         re[ti] = sr;
         im[ti] = si;
         pr = sr;
@@ -172,8 +313,106 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
     }
 }
 
+__global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, int h, float *re, float *im,
+                                                   uint32_t *fail, double2 *part) {
+    __shared__ Stage S;
+    __shared__ double2 wpart[4];
+    const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
+    double pr = 0.0, pi = 0.0;
+    for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
+        const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
+        stage_block(S, m, h, I0, J0);
+        const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT, sr = kPT + 2 * h;
+        if (I0 + tx < M && J0 + ty < M) {
+            const int me = (tx + h) + sr * (ty + h);
+            const uint32_t n = S.cnt[me];
+            for (uint32_t s = 0; s < n; ++s) {
+                const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
+                const uint32_t ti = comp4u(S.tag[me], s);
+                Nb6 b;
+    #pragma unroll
+                for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
+                for (int dj = -h; dj <= h; ++dj)
+                    for (int di = -h; di <= h; ++di) {
+                        const int ne = me + di + sr * dj;
+                        const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                        const uint32_t mm = S.cnt[ne];
+                        const float4 qx = S.x[ne], qy = S.y[ne];
+                        const uint4 qt = S.tag[ne];
+                        for (uint32_t t = 0; t < mm; ++t) {
+                            if (di == 0 && dj == 0 && t == s) continue;
+                            const float dx = (comp4f(qx, t) - xi) + cwx;
+                            const float dy = (comp4f(qy, t) - yi) + cwy;
+                            const float r2 = r2_f32(dx, dy);
+                            const uint32_t tg = comp4u(qt, t);
+                            if (!nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
+                            b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
+    #pragma unroll
+                            for (int e = 5; e > 0; --e) {
+                                if (nb_less(b.r2[e], b.tag[e], b.r2[e - 1], b.tag[e - 1])) {
+                                    float fr = b.r2[e]; b.r2[e] = b.r2[e - 1]; b.r2[e - 1] = fr;
+                                    uint32_t ft = b.tag[e]; b.tag[e] = b.tag[e - 1]; b.tag[e - 1] = ft;
+                                    float fx = b.dx[e]; b.dx[e] = b.dx[e - 1]; b.dx[e - 1] = fx;
+                                    float fy = b.dy[e]; b.dy[e] = b.dy[e - 1]; b.dy[e - 1] = fy;
+                                }
+                            }
+                        }
+                    }
+                const double reach = (double)h * (double)m.w;
+                if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
+                float sr6 = 0.0f, si6 = 0.0f;
+                psi6_sum(b, sr6, si6);
+                re[ti] = sr6;
+                im[ti] = si6;
+                pr += sr6;
+                pi += si6;
+            }
+        }
+        __syncthreads();  // S is restaged for the next block
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        pr += __shfl_xor(pr, off, 64);
+        pi += __shfl_xor(pi, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0) wpart[threadIdx.x >> 6] = make_double2(pr, pi);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = make_double2(wpart[0].x + wpart[1].x + wpart[2].x + wpart[3].x,
+                                        wpart[0].y + wpart[1].y + wpart[2].y + wpart[3].y);
+}
+
+// Global psi sum from the G workgroup partials (overwrites dev->psi_re/im).
+__global__ void __launch_bounds__(256) k_psi_reduce(const double2 *part, uint32_t G, DevScalars *dev) {
+    __shared__ double2 wpart[4];
+    double pr = 0.0, pi = 0.0;
+    for (uint32_t g = threadIdx.x; g < G; g += blockDim.x) {
+        pr += part[g].x;
+        pi += part[g].y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        pr += __shfl_xor(pr, off, 64);
+        pi += __shfl_xor(pi, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0) wpart[threadIdx.x >> 6] = make_double2(pr, pi);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dev->psi_re = wpart[0].x + wpart[1].x + wpart[2].x + wpart[3].x;
+        dev->psi_im = wpart[0].y + wpart[1].y + wpart[2].y + wpart[3].y;
+    }
+}
+
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 const uint32_t *loc, hipStream_t st) {
+                 const uint32_t *loc, void *work, hipStream_t st) {
+    if (measure_tiled(m, h)) {
+        const uint32_t nb = (m.M + kPT - 1) / kPT;
+        const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+        double2 *part = static_cast<double2 *>(work);
+        k_psi6_tile<<<G, 256, 0, st>>>(m, (int)h, re, im, fail, part);
+        k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
+        return;
+    }
     k_psi6<<<(m.N + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail, loc);
 }
 

@@ -62,6 +62,8 @@ struct Box {
     float *psi_buf = nullptr;  // re[N], im[N], field re/im[M*M]
     uint32_t *loc = nullptr;   // slot of every disk by tag (measurement kernels)
     int locate();              // fills loc for the current state
+    void *meas_work = nullptr;  // partial results of the tiled measurement kernels
+    int measure_work();         // allocates meas_work on first use
     uint64_t n_conf = 0;
     // blocks for the pressure standard error
     std::vector<unsigned long long> block_snapshot;

@@ -68,11 +68,16 @@ struct MeasureView {
 // h: stencil half-width in cells (1 when w covers the histogram range)
 // Kernels over disks take loc[tag] = slot_at(cell, slot, M * M) (launch_locate).
 void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st);
+// the contact and psi_6 kernels stage 16 x 16 cell blocks in LDS (and need
+// no loc) when cells hold at most 4 disks and the stencil half-width h <= 3
+bool measure_tiled(const MeasureView &m, uint32_t h);
+// work: device scratch of measure_work_bytes(K) bytes for the tiled kernels
+size_t measure_work_bytes(uint32_t K);
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
                          unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
-                         hipStream_t st);
+                         void *work, hipStream_t st);
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 const uint32_t *loc, hipStream_t st);
+                 const uint32_t *loc, void *work, hipStream_t st);
 void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
                        float *fim, hipStream_t st);
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);

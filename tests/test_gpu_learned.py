@@ -100,9 +100,10 @@ def test_learned_sampler_exact_for_two_disks(gpu_lib):
 def test_training_reduces_loss_and_learned_matches_plain(gpu_lib, tmp_path):
     """Collect accepted plain moves on a dense liquid, train, then compare
     the pressure of learned and plain runs (same box size, same w >= 3
-    grid), both continued from one equilibrated configuration.  The density
-    sits below the liquid-hexatic range, where the pressure decorrelates
-    within a few hundred sweeps and block errors are honest."""
+    grid).  Each sampler is continued from four independently equilibrated
+    configurations and the error comes from the scatter between those runs:
+    the block error of one run underestimates the true one by a factor of
+    two or more at this size, because the pressure decorrelates slowly."""
     cfg = dict(N=32 * 32, eta=0.65)
     box = gpu_lib.Box(**cfg, seed=7, step_m=40, cell_min=3.0, schedule="simple")
     L = gpu_lib.Learner(seed=3, capacity=1 << 18)
@@ -112,22 +113,25 @@ def test_training_reduces_loss_and_learned_matches_plain(gpu_lib, tmp_path):
     l1 = L.train(600, batch=2048, lr=1e-3)
     assert l1 < l0 - 0.3, (l0, l1)
     assert L.info()["feature_overflow"] == 0
-    eq = gpu_lib.Box(**cfg, seed=100, step_m=40, cell_min=3.0, schedule="simple",
-                     hist_bins=20, hist_dr=0.01, hist_block=500)
-    eq.sweep(4000)
-    start = str(tmp_path / "equilibrated.ckpt")
-    eq.save(start)
-    Ps = {}
-    for mode in ("plain", "learned"):
-        b = gpu_lib.Box.load(start, schedule="simple")
-        for _ in range(6000):
-            if mode == "plain":
-                b.sweep(2)
-            else:
-                gpu_lib.sweep_learned(b, L, 2, eps=0.1)
-            b.accumulate_contacts()
-        Ps[mode] = b.measure_pressure()
-        assert b.validate() == (0, 0)
-    d = Ps["learned"]["P_star"] - Ps["plain"]["P_star"]
-    se = math.hypot(Ps["learned"]["se"], Ps["plain"]["se"])
-    assert abs(d) < 3 * se, (Ps, d, se)
+    Ps = {"plain": [], "learned": []}
+    for seed in range(100, 104):
+        eq = gpu_lib.Box(**cfg, seed=seed, step_m=40, cell_min=3.0, schedule="simple",
+                         hist_bins=20, hist_dr=0.01, hist_block=500)
+        eq.sweep(3000)
+        start = str(tmp_path / ("equilibrated_%d.ckpt" % seed))
+        eq.save(start)
+        for mode in ("plain", "learned"):
+            b = gpu_lib.Box.load(start, schedule="simple")
+            for _ in range(3000):
+                if mode == "plain":
+                    b.sweep(2)
+                else:
+                    gpu_lib.sweep_learned(b, L, 2, eps=0.1)
+                b.accumulate_contacts()
+            Ps[mode].append(b.measure_pressure()["P_star"])
+            assert b.validate() == (0, 0)
+    p, q = np.array(Ps["plain"]), np.array(Ps["learned"])
+    se = math.sqrt(p.var(ddof=1) / len(p) + q.var(ddof=1) / len(q))
+    d = q.mean() - p.mean()
+    # 4 standard errors: about 1% false alarms with 6 degrees of freedom
+    assert abs(d) < 4 * se, (Ps, d, se)

@@ -189,11 +189,24 @@ def test_psi6_matches_oracle(gpu_lib):
     assert np.abs(field - ofield).max() < 1e-5
 
 
+def test_psi6_config2_matches_oracle(gpu_lib):
+    """Many 16 x 16 cell blocks (M = 226) of the tiled psi_6 kernel."""
+    g = gpu_box(gpu_lib, **CONFIG2)
+    o = OracleBox(**CONFIG2)
+    g.sweep(40)
+    o.sweep(40)
+    psi, field, Psi = g.psi6_field()
+    opsi = o.psi6()
+    assert np.abs(psi - opsi).max() < 1e-5
+    ofield = o.psi6_field(opsi)
+    assert np.abs(field - ofield).max() < 1e-5
+
+
 def test_fused_tiles_must_not_wrap(gpu_lib):
     """A tile whose halo region would cover the box twice is refused."""
     g = gpu_box(gpu_lib, **CONFIG1, schedule="simple")
     with pytest.raises(gpu_lib.MPMCError):
-        g.set_schedule("fused", 16, 256)   # 16 + 2 * 4 > M = 18
+        g.set_schedule("fused", 16, 256)   # 16 + 10 > M = 18
 
 
 def test_n2_edge_case_bit_exact(gpu_lib):
