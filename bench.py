@@ -24,8 +24,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# 32-bit vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per
+# lane and clock (packed fp32 excluded), in tera-operations per second
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 N_DISKS = 1024 * 1024
 ETA = 0.716
+# Algorithmic 32-bit operations of one trial: one Philox4x32-10 block (10
+# rounds of two 32x32->64 multiplies, counted as two operations each, and
+# four xors: 80), slot pick and step (7), new position (2), in-cell test (4),
+# accept (2): 95; plus one pair test (2 subtractions, 2 multiplications, 1
+# addition, 1 comparison: 6) per other disk of the 3 x 3 cell neighbourhood.
+ALU_OPS_TRIAL = 95
+ALU_OPS_PAIR = 6
 
 
 def algorithmic_bytes_per_sweep(N, M):
@@ -33,6 +43,12 @@ def algorithmic_bytes_per_sweep(N, M):
     (2 x 8 B per disk), every tag read and written (2 x 4 B per disk), every
     cell count read and written (2 x 1 B per cell)."""
     return 16 * N + 8 * N + 2 * M * M
+
+
+def alu_ops_per_trial(N, M):
+    """Algorithmic operations per trial with the mean number of other disks
+    in a 3 x 3 block of cells, 9 N / M^2 - 1."""
+    return ALU_OPS_TRIAL + ALU_OPS_PAIR * (9.0 * N / (M * M) - 1.0)
 
 
 def tune_step(box, target=0.30, rounds=6, block=100):
@@ -104,6 +120,7 @@ def learned_comparison(seed, minutes_budget=0.5):
     loss = L.train(3000, batch=8192, lr=1e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    progress("learned proposal trained on %d moves in %.1f s" % (n, train_s))
     out = {"train": {"moves": n, "steps": 3001, "batch": 8192, "loss_first": loss0,
                      "loss_last": loss, "seconds": train_s}}
     for mode in ("uniform", "learned"):
@@ -159,6 +176,10 @@ def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
                                                                      platform.machine()))
 
 
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +211,7 @@ def main():
         box.set_graphs(args.sweeps)  # one captured graph per benchmark step
         step_m, acc0 = tune_step(box)
         info = box.info()
+        progress("step tuned (m = %d), schedule %s tile %d" % (step_m, info["schedule"], info["tile"]))
         for _ in range(args.warmup):
             box.sweep(args.sweeps)
             box.accumulate_contacts()
@@ -213,12 +235,16 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         t_after = box.info()
+        progress("timed %d steps in %.3f s" % (args.steps, elapsed))
 
     trials = t_after["trials"] - t_before["trials"]
     accepts = t_after["accepts"] - t_before["accepts"]
     sweep_ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * args.sweeps)
     bytes_per = algorithmic_bytes_per_sweep(info["N"], info["M"])
-    achieved = bytes_per / (sweep_ms * 1e-3) / 1e9
+    achieved_gbs = bytes_per / (sweep_ms * 1e-3) / 1e9
+    trials_per_sweep = trials / (args.steps * args.sweeps)
+    ops_per = trials_per_sweep * alu_ops_per_trial(info["N"], info["M"])
+    achieved_tops = ops_per / (sweep_ms * 1e-3) / 1e12
     pressure = box.measure_pressure()
     overlaps, bad = box.validate()
 
@@ -246,21 +272,28 @@ def main():
         "sweeps_per_s": args.steps * args.sweeps / elapsed,
         "sweep_us": sweep_ms * 1e3,
         "acceptance": accepts / max(trials, 1),
-        "trials_per_sweep": trials / (args.steps * args.sweeps),
+        "trials_per_sweep": trials_per_sweep,
         "psi6_decorrelations_per_s": None,
         "P_star_sample": pressure["P_star"],
         "abs_Psi6_mean": sum(abs(p) for p in psi_series) / len(psi_series),
         "validate": {"overlaps": overlaps, "bad": bad},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": ALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved_tops / ALU_PEAK_TOPS,
+                     "traffic": stored_traffic(),
                      "kernel": "k_fused (one sweep per launch)",
-                     "algorithmic_bytes_per_launch": bytes_per,
+                     "algorithmic_ops_per_launch": ops_per,
+                     "ops_per_trial": alu_ops_per_trial(info["N"], info["M"]),
+                     "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved_gbs / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": bytes_per},
                      "kernel_digest": kernel_source_digest()},
     }
     if not args.no_learned:
         line["learned_vs_uniform"] = learned_comparison(args.seed)
+        progress("learned comparison done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(0, args.seed, step_m)
+        progress("cpu baseline done")
     print(json.dumps(line))
 
 

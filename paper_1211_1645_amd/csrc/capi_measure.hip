@@ -234,15 +234,15 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
         int rc = b->alloc_dev((void **)&b->psi_buf, (2 * (size_t)b->N + 2 * nc) * 4);
         if (rc) return rc;
     }
-    int rc = b->read_scalars();
-    if (rc) return rc;
     float *dre = b->psi_buf, *dim = dre + b->N, *dfr = dim + b->N, *dfi = dfr + nc;
     const uint32_t hmax = (M - 2) / 2;  // 2h + 1 <= M - 1: no cell seen twice
     uint32_t h = hmax < 2 ? hmax : 2;
     if (h < 1) return fail(MPMC_EINVAL, "box too small for the neighbour search");
-    rc = b->measure_work();
+    int rc = b->measure_work();
     if (rc) return rc;
     bool located = false;
+    // One host synchronisation per attempt: the field and the copies are
+    // queued behind the psi kernel and discarded if its search was too short.
     for (;;) {
         if (!measure_tiled(b->mview(), h) && !located) {
             rc = b->locate();
@@ -253,22 +253,21 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
         HIPCHK(hipMemsetAsync(b->scratch_u32, 0, 4, b->stream));
         launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->loc, b->meas_work, b->stream);
         HIPCHK(hipGetLastError());
+        launch_psi6_field(b->mview(), dre, dim, dfr, dfi, b->stream);
+        HIPCHK(hipGetLastError());
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (re) HIPCHK(hipMemcpyAsync(re, dre, (size_t)b->N * 4, kind, b->stream));
+        if (im) HIPCHK(hipMemcpyAsync(im, dim, (size_t)b->N * 4, kind, b->stream));
+        if (fre) HIPCHK(hipMemcpyAsync(fre, dfr, nc * 4, kind, b->stream));
+        if (fim) HIPCHK(hipMemcpyAsync(fim, dfi, nc * 4, kind, b->stream));
         uint32_t failed = 0;
         HIPCHK(hipMemcpyAsync(&failed, b->scratch_u32, 4, hipMemcpyDeviceToHost, b->stream));
-        HIPCHK(hipStreamSynchronize(b->stream));
+        rc = b->read_scalars();  // synchronises the stream
+        if (rc) return rc;
         if (!failed) break;
         if (h >= hmax) return fail(MPMC_EINVAL, "six nearest neighbours lie beyond %u cells", h);
         ++h;
     }
-    launch_psi6_field(b->mview(), dre, dim, dfr, dfi, b->stream);
-    HIPCHK(hipGetLastError());
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (re) HIPCHK(hipMemcpyAsync(re, dre, (size_t)b->N * 4, kind, b->stream));
-    if (im) HIPCHK(hipMemcpyAsync(im, dim, (size_t)b->N * 4, kind, b->stream));
-    if (fre) HIPCHK(hipMemcpyAsync(fre, dfr, nc * 4, kind, b->stream));
-    if (fim) HIPCHK(hipMemcpyAsync(fim, dfi, nc * 4, kind, b->stream));
-    rc = b->read_scalars();
-    if (rc) return rc;
     if (Psi_re) *Psi_re = b->host.psi_re / (double)b->N;
     if (Psi_im) *Psi_im = b->host.psi_im / (double)b->N;
     return MPMC_OK;
