@@ -68,38 +68,55 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
 }
 
 // ---------------------------------------------------------------------------
-// Tiled forms for boxes of at most 4 slots per cell: a workgroup of 256
-// threads owns a 16 x 16 block of cells, stages the block plus a halo of h
-// cells (count, offsets and tags of every slot in use) in LDS once, and each
-// thread then serves the disks of one cell from LDS.  Neighbouring disks
-// are read from the staged copy instead of being gathered from global
-// memory once per disk.
+// Tiled forms for boxes of at most 4 slots per cell.  A workgroup of 256
+// threads stages a 16 x 16 block of cells plus a halo of H cells in LDS
+// (offsets with a far sentinel in empty slots, tags, counts), lists the
+// block's disks and gives each lane one disk.  The stencil is unrolled over
+// its (2H+1)^2 cells and SL slots per cell (SL = 2, or 4 when some staged
+// cell holds more than two disks), so no lane runs a trip count of its own.
+// A persistent grid of at most kMeasGrid workgroups strides over the blocks
+// and leaves one partial result per workgroup, which a second kernel sums:
+// no two workgroups add to one address.
 constexpr int kPT = 16, kStageHalo = 3, kSR = kPT + 2 * kStageHalo;
+constexpr float kFarM = 1.0e6f;  // sentinel offset of an empty slot
+constexpr uint32_t kMeasGrid = 1024;
 
 struct Stage {
     float4 x[kSR * kSR], y[kSR * kSR];
     uint4 tag[kSR * kSR];
     uint8_t cnt[kSR * kSR];
+    uint16_t disk[4 * kPT * kPT];  // the block's disks: own cell << 2 | slot
+    uint32_t wsum[4], wbig[4];
 };
 
-__device__ __forceinline__ float comp4f(const float4 &v, uint32_t s) {
+size_t measure_work_bytes(uint32_t K) { return (size_t)kMeasGrid * (K * 4 + sizeof(double2)); }
+
+bool measure_tiled(const MeasureView &m, uint32_t h) {
+    return m.cap <= 4 && h >= 1 && h <= (uint32_t)kStageHalo;
+}
+
+__device__ __forceinline__ float comp4f(const float4 &v, int s) {
     return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
-__device__ __forceinline__ uint32_t comp4u(const uint4 &v, uint32_t s) {
+__device__ __forceinline__ uint32_t comp4u(const uint4 &v, int s) {
     return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
 }
 
-// Stages block (I0, J0) with halo h; region cell (rx, ry) is index rx + sr ry,
-// sr = 16 + 2 h.
-__device__ void stage_block(Stage &S, const MeasureView &m, int h, uint32_t I0, uint32_t J0) {
-    const int sr = kPT + 2 * h;
+// Stages block (I0, J0) with halo H (region cell (rx, ry) at rx + SR ry,
+// SR = 16 + 2H) and lists the block's disks.  Returns the number of listed
+// disks; *big tells whether some staged cell holds more than two.
+template <int H>
+__device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t J0, bool *big) {
+    constexpr int SR = kPT + 2 * H;
     const uint32_t M = m.M, NC = M * M;
-    for (int e = threadIdx.x; e < sr * sr; e += blockDim.x) {
-        const int rx = e % sr, ry = e / sr;
-        const uint32_t c = wrapc((int)I0 - h + rx, M) + M * wrapc((int)J0 - h + ry, M);
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    bool crowded = false;
+    for (int e = threadIdx.x; e < SR * SR; e += blockDim.x) {
+        const int rx = e % SR, ry = e / SR;
+        const uint32_t c = wrapc((int)I0 - H + rx, M) + M * wrapc((int)J0 - H + ry, M);
         uint32_t n = m.cnt[c];
         n = n > 4 ? 4 : n;
-        float4 x4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), y4 = x4;
+        float4 x4 = make_float4(kFarM, kFarM, kFarM, kFarM), y4 = x4;
         uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
         if (n > 0) { x4.x = m.x[c]; y4.x = m.y[c]; t4.x = m.tag[c]; }
         if (n > 1) { x4.y = m.x[NC + c]; y4.y = m.y[NC + c]; t4.y = m.tag[NC + c]; }
@@ -109,65 +126,96 @@ __device__ void stage_block(Stage &S, const MeasureView &m, int h, uint32_t I0, 
         S.y[e] = y4;
         S.tag[e] = t4;
         S.cnt[e] = (uint8_t)n;
+        crowded |= n > 2;
+    }
+    // this thread's own cell and its disk count; prefix sums over the block
+    // from bit-plane ballots (a count is below 8)
+    const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT;
+    const bool inb = I0 + tx < M && J0 + ty < M;
+    uint32_t nown = 0;
+    if (inb) {
+        const uint32_t c = wrapc((int)I0 + tx, M) + M * wrapc((int)J0 + ty, M);
+        nown = m.cnt[c];
+        nown = nown > 4 ? 4 : nown;
+    }
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const unsigned long long bb = __ballot((nown >> b) & 1u);
+        pre += (uint32_t)__popcll(bb & lt) << b;
+        tot += (uint32_t)__popcll(bb) << b;
+    }
+    const unsigned long long bg = __ballot(crowded);
+    if (lane == 0) {
+        S.wsum[wave] = tot;
+        S.wbig[wave] = bg != 0ull;
     }
     __syncthreads();
+    uint32_t off = 0, all = 0, anybig = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        off += q < wave ? S.wsum[q] : 0u;
+        all += S.wsum[q];
+        anybig |= S.wbig[q];
+    }
+    for (uint32_t k = 0; k < nown; ++k) S.disk[off + pre + k] = (uint16_t)((threadIdx.x << 2) | k);
+    __syncthreads();
+    *big = anybig != 0;
+    return (int)all;
 }
 
-// The tiled kernels run a persistent grid of at most kMeasGrid workgroups
-// over the 16 x 16 blocks and leave one partial result per workgroup, which
-// a second kernel sums: no two workgroups ever add to the same address.
-constexpr uint32_t kMeasGrid = 1024;
+// Ordered contact pairs of the listed disks into the LDS bins.
+template <int H, int SL>
+__device__ void contact_disks(const Stage &S, const MeasureView &m, const float *__restrict__ E,
+                              uint32_t K, const uint8_t *sel, int ndisk, uint32_t *bins) {
+    constexpr int SR = kPT + 2 * H;
+    const float e0 = E[0], eK = E[K];
+    for (int j = threadIdx.x; j < ndisk; j += blockDim.x) {
+        const uint32_t d = S.disk[j];
+        const int cl = (int)(d >> 2), s = (int)(d & 3u);
+        const int me = (cl % kPT + H) + SR * (cl / kPT + H);
+        if (sel && !sel[comp4u(S.tag[me], s)]) continue;
+        const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
+#pragma unroll
+        for (int dj = -H; dj <= H; ++dj)
+#pragma unroll
+            for (int di = -H; di <= H; ++di) {
+                const int ne = me + di + SR * dj;
+                const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                const float4 qx = S.x[ne], qy = S.y[ne];
+#pragma unroll
+                for (int q = 0; q < SL; ++q) {
+                    const float dx = (comp4f(qx, q) - xi) + cwx;
+                    const float dy = (comp4f(qy, q) - yi) + cwy;
+                    const float r2 = r2_f32(dx, dy);
+                    const bool self = di == 0 && dj == 0 && q == s;
+                    if (self || !(r2 >= e0) || !(r2 < eK)) continue;
+                    // start from the square-root estimate, then settle on
+                    // the exact fp32 edges
+                    int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
+                    k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
+                    while (k > 0 && r2 < E[k]) --k;
+                    while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
+                    atomicAdd(&bins[k], 1u);
+                }
+            }
+    }
+}
 
+template <int H>
 __global__ void __launch_bounds__(256) k_contact_hist_tile(MeasureView m, const float *__restrict__ E,
-                                                           uint32_t K, int h, const uint8_t *sel,
+                                                           uint32_t K, const uint8_t *sel,
                                                            uint32_t *rows) {
     __shared__ Stage S;
     extern __shared__ uint32_t bins[];
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
     const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
-    const float e0 = E[0], eK = E[K];
-    const float rmax = sqrtf(eK) * 1.0001f + 1e-4f;  // conservative reach
     for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
-        const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
-        stage_block(S, m, h, I0, J0);  // ends with a barrier
-        const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT, sr = kPT + 2 * h;
-        if (I0 + tx < M && J0 + ty < M) {
-            const int me = (tx + h) + sr * (ty + h);
-            const uint32_t n = S.cnt[me];
-            for (uint32_t s = 0; s < n; ++s) {
-                if (sel && !sel[comp4u(S.tag[me], s)]) continue;
-                const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
-                for (int dj = -h; dj <= h; ++dj) {
-                    // smallest |dy| to any disk of row dj: skip rows out of reach
-                    const float gy = dj > 1 ? (float)(dj - 1) * m.w + (m.w - yi)
-                                   : dj < -1 ? (float)(-dj - 1) * m.w + yi : 0.0f;
-                    if (gy > rmax) continue;
-                    for (int di = -h; di <= h; ++di) {
-                        const float gx = di > 1 ? (float)(di - 1) * m.w + (m.w - xi)
-                                       : di < -1 ? (float)(-di - 1) * m.w + xi : 0.0f;
-                        if (gx > rmax) continue;
-                        const int ne = me + di + sr * dj;
-                        const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
-                        const uint32_t mm = S.cnt[ne];
-                        const float4 qx = S.x[ne], qy = S.y[ne];
-                        for (uint32_t q = 0; q < mm; ++q) {
-                            if (di == 0 && dj == 0 && q == s) continue;
-                            const float dx = (comp4f(qx, q) - xi) + cwx;
-                            const float dy = (comp4f(qy, q) - yi) + cwy;
-                            const float r2 = r2_f32(dx, dy);
-                            if (!(r2 >= e0) || !(r2 < eK)) continue;
-                            // start from the square-root estimate, then settle
-                            // on the exact fp32 edges
-                            int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
-                            k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
-                            while (k > 0 && r2 < E[k]) --k;
-                            while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
-                            atomicAdd(&bins[k], 1u);
-                        }
-                    }
-                }
-            }
-        }
+        bool big;
+        const int nd = stage_block<H>(S, m, (blk % nbx) * kPT, (blk / nbx) * kPT, &big);
+        if (big) contact_disks<H, 4>(S, m, E, K, sel, nd, bins);
+        else contact_disks<H, 2>(S, m, E, K, sel, nd, bins);
         __syncthreads();  // S is restaged for the next block
     }
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) rows[blockIdx.x * K + k] = bins[k];
@@ -187,6 +235,18 @@ __global__ void __launch_bounds__(256) k_hist_rows_reduce(const uint32_t *rows, 
     if (threadIdx.x == 0) hist[k] += part[0] + part[1] + part[2] + part[3];
 }
 
+void launch_contact_tiled(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
+                          unsigned long long *hist, const uint8_t *sel, void *work, hipStream_t st) {
+    const uint32_t nb = (m.M + kPT - 1) / kPT;
+    const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+    uint32_t *rows = static_cast<uint32_t *>(work);
+    const size_t lds = K * sizeof(uint32_t);
+    if (h == 1) k_contact_hist_tile<1><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
+    else if (h == 2) k_contact_hist_tile<2><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
+    else k_contact_hist_tile<3><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
+    k_hist_rows_reduce<<<K, 256, 0, st>>>(rows, G, K, hist);
+}
+
 // Slot of every disk by tag: loc[tag] = slot_at(cell, slot, M * M).
 __global__ void __launch_bounds__(256) k_locate(MeasureView m, uint32_t *loc) {
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,21 +261,11 @@ void launch_locate(const MeasureView &m, uint32_t *loc, hipStream_t st) {
     k_locate<<<(n + 255) / 256, 256, 0, st>>>(m, loc);
 }
 
-bool measure_tiled(const MeasureView &m, uint32_t h) {
-    return m.cap <= 4 && h <= (uint32_t)kStageHalo;
-}
-
-size_t measure_work_bytes(uint32_t K) { return (size_t)kMeasGrid * (K * 4 + sizeof(double2)); }
-
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
                          unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
                          void *work, hipStream_t st) {
     if (measure_tiled(m, h)) {
-        const uint32_t nb = (m.M + kPT - 1) / kPT;
-        const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
-        uint32_t *rows = static_cast<uint32_t *>(work);
-        k_contact_hist_tile<<<G, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, sel, rows);
-        k_hist_rows_reduce<<<K, 256, 0, st>>>(rows, G, K, hist);
+        launch_contact_tiled(m, edges, K, h, hist, sel, work, st);
         return;
     }
     k_contact_hist<<<(m.N + 255) / 256, 256, K * sizeof(uint32_t), st>>>(m, edges, K, (int)h, hist,
@@ -313,61 +363,74 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
     }
 }
 
-__global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, int h, float *re, float *im,
+// psi_j of the listed disks; returns this lane's contribution to the sums.
+template <int H, int SL>
+__device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, float *re, float *im,
+                           uint32_t *fail, double &pr, double &pi) {
+    constexpr int SR = kPT + 2 * H;
+    for (int j = threadIdx.x; j < ndisk; j += blockDim.x) {
+        const uint32_t d = S.disk[j];
+        const int cl = (int)(d >> 2), s = (int)(d & 3u);
+        const int me = (cl % kPT + H) + SR * (cl / kPT + H);
+        const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
+        const uint32_t ti = comp4u(S.tag[me], s);
+        Nb6 b;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
+#pragma unroll 1
+        for (int dj = -H; dj <= H; ++dj)
+#pragma unroll
+            for (int di = -H; di <= H; ++di) {
+                const int ne = me + di + SR * dj;
+                const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+                const float4 qx = S.x[ne], qy = S.y[ne];
+                const uint4 qt = S.tag[ne];
+#pragma unroll
+                for (int q = 0; q < SL; ++q) {
+                    const float dx = (comp4f(qx, q) - xi) + cwx;
+                    const float dy = (comp4f(qy, q) - yi) + cwy;
+                    // empty slots hold a far sentinel: they can only enter a
+                    // list that then fails the reach test below
+                    const float r2 = r2_f32(dx, dy);
+                    const uint32_t tg = comp4u(qt, q);
+                    const bool self = di == 0 && dj == 0 && q == s;
+                    if (self || !nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
+                    b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
+#pragma unroll
+                    for (int e = 5; e > 0; --e) {
+                        if (nb_less(b.r2[e], b.tag[e], b.r2[e - 1], b.tag[e - 1])) {
+                            float fr = b.r2[e]; b.r2[e] = b.r2[e - 1]; b.r2[e - 1] = fr;
+                            uint32_t ft = b.tag[e]; b.tag[e] = b.tag[e - 1]; b.tag[e - 1] = ft;
+                            float fx = b.dx[e]; b.dx[e] = b.dx[e - 1]; b.dx[e - 1] = fx;
+                            float fy = b.dy[e]; b.dy[e] = b.dy[e - 1]; b.dy[e - 1] = fy;
+                        }
+                    }
+                }
+            }
+        // exact only if every disk closer than the sixth lies in the stencil
+        const double reach = (double)H * (double)m.w;
+        if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
+        float sr6 = 0.0f, si6 = 0.0f;
+        psi6_sum(b, sr6, si6);
+        re[ti] = sr6;
+        im[ti] = si6;
+        pr += sr6;
+        pi += si6;
+    }
+}
+
+template <int H>
+__global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, float *im,
                                                    uint32_t *fail, double2 *part) {
     __shared__ Stage S;
     __shared__ double2 wpart[4];
     const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
     double pr = 0.0, pi = 0.0;
     for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
-        const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
-        stage_block(S, m, h, I0, J0);
-        const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT, sr = kPT + 2 * h;
-        if (I0 + tx < M && J0 + ty < M) {
-            const int me = (tx + h) + sr * (ty + h);
-            const uint32_t n = S.cnt[me];
-            for (uint32_t s = 0; s < n; ++s) {
-                const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
-                const uint32_t ti = comp4u(S.tag[me], s);
-                Nb6 b;
-    #pragma unroll
-                for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
-                for (int dj = -h; dj <= h; ++dj)
-                    for (int di = -h; di <= h; ++di) {
-                        const int ne = me + di + sr * dj;
-                        const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
-                        const uint32_t mm = S.cnt[ne];
-                        const float4 qx = S.x[ne], qy = S.y[ne];
-                        const uint4 qt = S.tag[ne];
-                        for (uint32_t t = 0; t < mm; ++t) {
-                            if (di == 0 && dj == 0 && t == s) continue;
-                            const float dx = (comp4f(qx, t) - xi) + cwx;
-                            const float dy = (comp4f(qy, t) - yi) + cwy;
-                            const float r2 = r2_f32(dx, dy);
-                            const uint32_t tg = comp4u(qt, t);
-                            if (!nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
-                            b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
-    #pragma unroll
-                            for (int e = 5; e > 0; --e) {
-                                if (nb_less(b.r2[e], b.tag[e], b.r2[e - 1], b.tag[e - 1])) {
-                                    float fr = b.r2[e]; b.r2[e] = b.r2[e - 1]; b.r2[e - 1] = fr;
-                                    uint32_t ft = b.tag[e]; b.tag[e] = b.tag[e - 1]; b.tag[e - 1] = ft;
-                                    float fx = b.dx[e]; b.dx[e] = b.dx[e - 1]; b.dx[e - 1] = fx;
-                                    float fy = b.dy[e]; b.dy[e] = b.dy[e - 1]; b.dy[e - 1] = fy;
-                                }
-                            }
-                        }
-                    }
-                const double reach = (double)h * (double)m.w;
-                if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
-                float sr6 = 0.0f, si6 = 0.0f;
-                psi6_sum(b, sr6, si6);
-                re[ti] = sr6;
-                im[ti] = si6;
-                pr += sr6;
-                pi += si6;
-            }
-        }
+        bool big;
+        const int nd = stage_block<H>(S, m, (blk % nbx) * kPT, (blk / nbx) * kPT, &big);
+        if (big) psi6_disks<H, 4>(S, m, nd, re, im, fail, pr, pi);
+        else psi6_disks<H, 2>(S, m, nd, re, im, fail, pr, pi);
         __syncthreads();  // S is restaged for the next block
     }
 #pragma unroll
@@ -403,14 +466,21 @@ __global__ void __launch_bounds__(256) k_psi_reduce(const double2 *part, uint32_
     }
 }
 
+void launch_psi6_tiled(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
+                       void *work, hipStream_t st) {
+    const uint32_t nb = (m.M + kPT - 1) / kPT;
+    const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+    double2 *part = static_cast<double2 *>(work);
+    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, fail, part);
+    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, fail, part);
+    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, fail, part);
+    k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
+}
+
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
                  const uint32_t *loc, void *work, hipStream_t st) {
     if (measure_tiled(m, h)) {
-        const uint32_t nb = (m.M + kPT - 1) / kPT;
-        const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
-        double2 *part = static_cast<double2 *>(work);
-        k_psi6_tile<<<G, 256, 0, st>>>(m, (int)h, re, im, fail, part);
-        k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
+        launch_psi6_tiled(m, h, re, im, fail, work, st);
         return;
     }
     k_psi6<<<(m.N + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail, loc);
