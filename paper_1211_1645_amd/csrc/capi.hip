@@ -70,10 +70,10 @@ int mpmc::compute_geometry(Geometry *g, uint32_t N, double eta, double cell_min,
     g->Lq = (int64_t)g->M * g->W;
     g->cap = cell_capacity(w);
     g->CS = g->cap <= 4 ? 4 : 8;
-    // slot indices s * M^2 + c are 32-bit on the device
-    if ((uint64_t)g->M * g->M * g->CS > 0xFFFFFFFFull)
-        return fail(MPMC_EINVAL, "box too large: %u^2 cells x %u slots exceed 32-bit indexing", g->M,
-                    g->CS);
+    // slot indices s * M^2 + c and their byte offsets are 32-bit on the device
+    if ((uint64_t)g->M * g->M * g->CS * 4 > 0xFFFFFFFFull)
+        return fail(MPMC_EINVAL, "box too large: %u^2 cells x %u slots exceed 32-bit byte offsets",
+                    g->M, g->CS);
     return MPMC_OK;
 }
 

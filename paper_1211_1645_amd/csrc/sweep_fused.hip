@@ -96,6 +96,14 @@ __device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t M) {
     return (uint32_t)v;
 }
 
+// Element i of a buffer through a 32-bit byte offset, so that the access
+// compiles to a scalar base plus one 32-bit vector offset (every buffer of a
+// box is below 4 GiB, which the geometry check guarantees).
+template <typename T>
+__device__ __forceinline__ T &el(T *p, uint32_t i) {
+    return *(T *)((char *)p + i * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ float pick4(const float4 &v, uint32_t s) {
     const float a = (s & 1u) ? v.y : v.x;
     const float b = (s & 1u) ? v.w : v.z;
@@ -230,7 +238,7 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
         const int rx = 2 * ax + CX, ry = 2 * ay + CY;
         const int e = PB + a;
         const uint32_t n = L.cnt[e];
-        const uint32_t cell = wrap_add(ctx.gx0, rx, M) + M * wrap_add(ctx.gy0, ry, M);
+        const uint32_t cell = wrap_add(ctx.gx0, rx, M) + __umul24(M, wrap_add(ctx.gy0, ry, M));
         const bool own = (rx - kHalo) >= 0 && (rx - kHalo) < ctx.own_x && (ry - kHalo) >= 0 &&
                          (ry - kHalo) < ctx.own_y;
         uint32_t perm = 0x3210u;  // 4-bit slot fields
@@ -286,8 +294,9 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     const uint32_t gx0 = wrap_add(I0, -kHalo, M), gy0 = wrap_add(J0, -kHalo, M);
 
     // ---- load the region ----------------------------------------------------
-    // Counts and slot 0 (most cells hold one disk) are loaded together, the
-    // other slots where the count asks for them.
+    // Counts and slots 0 and 1 are loaded together (slot 1 is read whether
+    // used or not: one dependent round trip fewer), slots 2 and 3 where the
+    // count asks for them.
     if (tid == 0) L.big = 0u;
     uint32_t m_r[NIT], c_r[NIT];
     float4 px_r[NIT], py_r[NIT];
@@ -295,26 +304,22 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     for (int i = 0; i < NIT; ++i) {
         const int e = tid + i * THREADS;
         const int ee = e < NL ? e : 0;
-        const uint32_t c = wrap_add(gx0, ee % RL, M) + M * wrap_add(gy0, ee / RL, M);
+        const uint32_t c = wrap_add(gx0, ee % RL, M) + __umul24(M, wrap_add(gy0, ee / RL, M));
         c_r[i] = c;
-        const uint32_t m = v.cnt_in[c];
+        const uint32_t m = el(v.cnt_in, c);
         m_r[i] = e < NL ? m : 0u;
-        px_r[i] = make_float4(v.x_in[c], kFar, kFar, kFar);
-        py_r[i] = make_float4(v.y_in[c], kFar, kFar, kFar);
+        px_r[i] = make_float4(el(v.x_in, c), el(v.x_in, NC + c), kFar, kFar);
+        py_r[i] = make_float4(el(v.y_in, c), el(v.y_in, NC + c), kFar, kFar);
     }
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const uint32_t c = c_r[i], m = m_r[i];
-        if (m > 1) {
-            px_r[i].y = v.x_in[NC + c];
-            py_r[i].y = v.y_in[NC + c];
-            if (m > 2) {
-                px_r[i].z = v.x_in[2 * NC + c];
-                py_r[i].z = v.y_in[2 * NC + c];
-                if (m > 3) {
-                    px_r[i].w = v.x_in[3 * NC + c];
-                    py_r[i].w = v.y_in[3 * NC + c];
-                }
+        if (m > 2) {
+            px_r[i].z = el(v.x_in, 2 * NC + c);
+            py_r[i].z = el(v.y_in, 2 * NC + c);
+            if (m > 3) {
+                px_r[i].w = el(v.x_in, 3 * NC + c);
+                py_r[i].w = el(v.y_in, 3 * NC + c);
             }
         }
     }
@@ -350,11 +355,11 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         tg_r[i] = make_uint4(0u, 0u, 0u, 0u);
         if (f < NE && ex <= own_x && ey <= own_y) {
             const uint32_t m = L.cnt[pidx<R>(ex + kHalo, ey + kHalo)];
-            const uint32_t c = wrap_add(I0, ex, M) + M * wrap_add(J0, ey, M);
-            if (m > 0) tg_r[i].x = v.tag_in[c];
-            if (m > 1) tg_r[i].y = v.tag_in[NC + c];
-            if (m > 2) tg_r[i].z = v.tag_in[2 * NC + c];
-            if (m > 3) tg_r[i].w = v.tag_in[3 * NC + c];
+            const uint32_t c = wrap_add(I0, ex, M) + __umul24(M, wrap_add(J0, ey, M));
+            if (m > 0) tg_r[i].x = el(v.tag_in, c);
+            if (m > 1) tg_r[i].y = el(v.tag_in, NC + c);
+            if (m > 2) tg_r[i].z = el(v.tag_in, 2 * NC + c);
+            if (m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
         }
     }
 
@@ -415,14 +420,14 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         ux_r[i] = ux;
         uy_r[i] = uy;
         if (in_ext && ex < own_x && ey < own_y && v.cnt_can) {
-            const uint32_t c = (I0 + ex) + M * (J0 + ey);
-            v.cnt_can[c] = (uint8_t)m;
+            const uint32_t c = (I0 + ex) + __umul24(M, J0 + ey);
+            el(v.cnt_can, c) = (uint8_t)m;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 if ((uint32_t)s < m) {
-                    v.x_can[s * NC + c] = comp4(ux, s);
-                    v.y_can[s * NC + c] = comp4(uy, s);
-                    v.tag_can[s * NC + c] = s == 0 ? tg_r[i].x : s == 1 ? tg_r[i].y
+                    el(v.x_can, s * NC + c) = comp4(ux, s);
+                    el(v.y_can, s * NC + c) = comp4(uy, s);
+                    el(v.tag_can, s * NC + c) = s == 0 ? tg_r[i].x : s == 1 ? tg_r[i].y
                                           : s == 2 ? tg_r[i].z : tg_r[i].w;
                 }
             }
@@ -462,6 +467,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         const uint32_t b3 = (g_dl & 7u) + ((g_d >> 3) & 7u) + ((g_l >> 6) & 7u);
         const uint32_t bases = (b1 << 8) | (b2 << 16) | (b3 << 24);
         uint32_t seen = 0;  // 3-bit counters per class within this old cell
+        const uint32_t nc0 = (I0 + ex) + __umul24(M, J0 + ey);  // new cell (ex, ey)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if ((uint32_t)s >= m) break;
@@ -471,10 +477,10 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             seen += 1u << (3 * cls);
             const int nx = ex - (int)wx, ny = ey - (int)wy;
             if (nx < 0 || nx >= own_x || ny < 0 || ny >= own_y || slot >= 4) continue;
-            const uint32_t nc = (I0 + nx) + M * (J0 + ny);
-            v.x_out[slot * NC + nc] = (us - sxn) + (wx ? w : 0.0f);
-            v.y_out[slot * NC + nc] = (vs - syn) + (wy ? w : 0.0f);
-            v.tag_out[slot * NC + nc] = s == 0 ? tg.x : s == 1 ? tg.y : s == 2 ? tg.z : tg.w;
+            const uint32_t at = nc0 - wx - (wy ? M : 0u) + slot * NC;
+            el(v.x_out, at) = (us - sxn) + (wx ? w : 0.0f);
+            el(v.y_out, at) = (vs - syn) + (wy ? w : 0.0f);
+            el(v.tag_out, at) = s == 0 ? tg.x : s == 1 ? tg.y : s == 2 ? tg.z : tg.w;
         }
         if (ex < own_x && ey < own_y) {  // the count of new cell (ex, ey)
             const uint32_t g_me = L.gcnt[f];
@@ -484,7 +490,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             const uint32_t n = (g_me & 7u) + ((g_r >> 3) & 7u) + ((g_u >> 6) & 7u) +
                                ((g_ur >> 9) & 7u);
             if (n > 4) atomicOr((uint32_t *)&v.dev->overflow, 1u);
-            v.cnt_out[(I0 + ex) + M * (J0 + ey)] = (uint8_t)(n > 4 ? 4 : n);
+            el(v.cnt_out, nc0) = (uint8_t)(n > 4 ? 4 : n);
         }
     }
     count_trials((DevScalars *)v.dev, trials, accepts);
