@@ -438,6 +438,80 @@ uint64_t orc_count_overlaps(const orc_box *b) {
     return n;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Positional order, Sec. IV.D: the structure factor, chi_j, and the
+ * positional correlation function C_q(r) averaged over pairs in a window of
+ * half-width sigma around r. */
+
+void orc_structure_factor(const orc_box *b, const int32_t *hk, uint32_t nq, double *S) {
+    int64_t *X, *Y;
+    all_positions(b, &X, &Y);
+    for (uint32_t iq = 0; iq < nq; ++iq) {
+        int64_t h = hk[2 * iq], k = hk[2 * iq + 1];
+        double re = 0.0, im = 0.0;
+        for (uint32_t n = 0; n < b->N; ++n) {
+            /* phase 2 pi (h X + k Y) / Lq, reduced exactly */
+            int64_t t = (int64_t)(((__int128)h * X[n] + (__int128)k * Y[n]) % b->Lq);
+            if (t < 0) t += b->Lq;
+            double ph = 2.0 * M_PI * ((double)t / (double)b->Lq);
+            re += cos(ph);
+            im += sin(ph);
+        }
+        S[iq] = (re * re + im * im) / (double)b->N;
+    }
+    free(X); free(Y);
+}
+
+void orc_chi(const orc_box *b, int32_t h, int32_t k, double *re, double *im) {
+    int64_t *X, *Y;
+    all_positions(b, &X, &Y);
+    for (uint32_t n = 0; n < b->N; ++n) {
+        int64_t t = (int64_t)(((__int128)h * X[n] + (__int128)k * Y[n]) % b->Lq);
+        if (t < 0) t += b->Lq;
+        double ph = 2.0 * M_PI * ((double)t / (double)b->Lq);
+        re[n] = cos(ph);
+        im[n] = sin(ph);
+    }
+    free(X); free(Y);
+}
+
+int orc_cq(const orc_box *b, double qx, double qy, double dr, uint32_t B, double *num,
+           int64_t *cnt) {
+    const double L_eff = (double)b->Lq * QD;
+    const double Dr = ldexp(dr, Q_SHIFT);
+    if (B == 0 || Dr != floor(Dr) || Dr <= 0.0) return -1;
+    const double top = (double)(B - 1) * dr + 1.0;
+    if (!(top < 0.5 * L_eff) || !(top < 512.0)) return -1;
+    const int64_t Rq = (int64_t)Dr, one = (int64_t)1 << Q_SHIFT;
+    int64_t *X, *Y;
+    all_positions(b, &X, &Y);
+    for (uint32_t n = 0; n < b->N; ++n)
+        for (uint32_t m = n + 1; m < b->N; ++m) {
+            int64_t dx = min_image(X[m] - X[n], b->Lq), dy = min_image(Y[m] - Y[n], b->Lq);
+            const int64_t reach = (int64_t)ldexp(top, Q_SHIFT);
+            if (llabs(dx) > reach || llabs(dy) > reach) continue;
+            const uint64_t d2 = (uint64_t)(dx * dx) + (uint64_t)(dy * dy);
+            const double phase = qx * ((double)dx * QD) + qy * ((double)dy * QD);
+            const double c = cos(phase);
+            /* candidate windows from the distance, each confirmed exactly */
+            const double d = sqrt((double)d2) * QD;
+            int64_t b0 = (int64_t)floor((d - 1.0) / dr) - 1, b1 = (int64_t)ceil((d + 1.0) / dr) + 1;
+            if (b0 < 0) b0 = 0;
+            if (b1 > (int64_t)B - 1) b1 = (int64_t)B - 1;
+            for (int64_t bb = b0; bb <= b1; ++bb) {
+                /* window [r_b - 1, r_b + 1] in q units, squared exactly */
+                const int64_t R = (int64_t)bb * Rq;
+                const int64_t lo = R > one ? R - one : 0, hi = R + one;
+                if (d2 >= (uint64_t)(lo * lo) && d2 <= (uint64_t)(hi * hi)) {
+                    num[bb] += c;
+                    cnt[bb] += 1;
+                }
+            }
+        }
+    free(X); free(Y);
+    return 0;
+}
+
 void orc_hist_edges(uint32_t K, double dr, float *E) {
     for (uint32_t k = 0; k <= K; ++k) {
         double e = 2.0 + (double)k * dr;

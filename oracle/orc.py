@@ -56,6 +56,11 @@ def lib():
         L.orc_pressure.restype = C.c_int
         L.orc_psi6.argtypes = [p, C.c_void_p, f64p, f64p]
         L.orc_psi6_field.argtypes = [p, f64p, f64p, f64p, f64p]
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        L.orc_structure_factor.argtypes = [p, i32p, C.c_uint32, f64p]
+        L.orc_chi.argtypes = [p, C.c_int32, C.c_int32, f64p, f64p]
+        L.orc_cq.argtypes = [p, C.c_double, C.c_double, C.c_double, C.c_uint32, f64p, i64p]
+        L.orc_cq.restype = C.c_int
         L.orc_acf.argtypes = [f64p, f64p, C.c_uint32, C.c_uint32, f64p]
         L.orc_tau_fit.argtypes = [f64p, C.c_uint32, C.c_double, C.c_double]
         L.orc_tau_fit.restype = C.c_double
@@ -250,6 +255,26 @@ class OracleBox:
         lib().orc_psi6_field(self.h, np.ascontiguousarray(psi.real), np.ascontiguousarray(psi.imag),
                              fre, fim)
         return fre + 1j * fim
+
+    def structure_factor(self, hk):
+        hk = np.ascontiguousarray(hk, np.int32).reshape(-1, 2)
+        S = np.zeros(len(hk), np.float64)
+        lib().orc_structure_factor(self.h, hk, len(hk), S)
+        return S
+
+    def chi(self, h, k):
+        re = np.zeros(self.N, np.float64)
+        im = np.zeros(self.N, np.float64)
+        lib().orc_chi(self.h, h, k, re, im)
+        return re + 1j * im
+
+    def cq(self, qx, qy, dr, B):
+        """Sums of cos(q.d) and pair counts per window r_b = b dr."""
+        num = np.zeros(B, np.float64)
+        cnt = np.zeros(B, np.int64)
+        if lib().orc_cq(self.h, qx, qy, dr, B, num, cnt) != 0:
+            raise ValueError("bins out of range")
+        return num, cnt
 
     def features(self, cell, self_tag, x, y):
         f = np.zeros(24, np.float32)

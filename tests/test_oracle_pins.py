@@ -479,3 +479,114 @@ def test_adam_first_step():
     p0 = p.copy()
     orc.adam(p, m, v, g, 1e-3, 1)
     assert np.allclose(p, p0 - 1e-3 * g / (np.abs(g) + 1e-8), atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Positional order (Sec. IV.D): S(q), chi_j and C_q(r)
+def _square_lattice(n, eta):
+    """n x n square lattice placed at (i + 1/2) Lq / n in q units."""
+    b = OracleBox(n * n, eta, lattice=2)
+    Lq = b.info()["W"] * b.info()["M"]
+    i = np.arange(n)
+    X = ((2 * i + 1) * Lq) // (2 * n)
+    XX, YY = np.meshgrid(X, X)
+    b.set_positions_q(XX.ravel(), YY.ravel())
+    return b, Lq
+
+
+def test_structure_factor_square_lattice_selection_rules():
+    """On an n x n lattice, rho(q) factorises into two geometric sums that
+    vanish unless h and k are both multiples of n; at (n, 0), (0, n) and
+    (n, n) every phase agrees (S = N up to the sub-q placement)."""
+    n = 16
+    b, Lq = _square_lattice(n, 0.5)
+    hk = [(n, 0), (0, n), (n, n), (2 * n, -n), (1, 0), (0, 3), (5, 7), (n + 1, 0), (n, 1)]
+    S = b.structure_factor(hk)
+    N = n * n
+    for (h, k), s in zip(hk, S):
+        if h % n == 0 and k % n == 0:
+            assert abs(s - N) < 1e-6 * N, (h, k, s)
+        else:
+            assert s < 1e-6 * N, (h, k, s)
+
+
+def test_structure_factor_two_disks_closed_form():
+    """N = 2: S(q) = |e^{i phi_1} + e^{i phi_2}|^2 / 2 = 1 + cos(q.(x_1 - x_2))."""
+    b = OracleBox(2, 0.04, lattice=2)
+    i = b.info()
+    Lq = i["W"] * i["M"]
+    X = np.array([123456789, 987654321], np.int64) % Lq
+    Y = np.array([55555555, 33333333], np.int64) % Lq
+    b.set_positions_q(X, Y)
+    hk = np.array([(1, 0), (3, -2), (7, 11), (-5, 4)], np.int32)
+    S = b.structure_factor(hk)
+    for (h, k), s in zip(hk, S):
+        dph = 2 * math.pi * ((h * (X[0] - X[1]) + k * (Y[0] - Y[1])) % Lq) / Lq
+        assert abs(s - (1 + math.cos(dph))) < 1e-12
+
+
+def test_structure_factor_ideal_gas_mean_one():
+    """Uniform independent positions: <S(q)> = 1 for every q != 0."""
+    rng = np.random.default_rng(5)
+    b = OracleBox(4096, 0.05, lattice=2)
+    i = b.info()
+    Lq = i["W"] * i["M"]
+    X = rng.integers(0, Lq, 4096)
+    Y = rng.integers(0, Lq, 4096)
+    b.set_positions_q(X, Y)
+    hk = [(h, k) for h in range(1, 21) for k in range(-10, 10)]
+    S = b.structure_factor(hk)
+    # S is exponential with mean 1 for each q: 400 samples
+    assert abs(S.mean() - 1.0) < 4 * S.std() / math.sqrt(len(S))
+
+
+def test_chi_square_lattice():
+    n = 16
+    b, Lq = _square_lattice(n, 0.5)
+    chi = b.chi(n, 0)
+    # phases 2 pi (i + 1/2): chi = -1 for every disk
+    assert np.abs(chi + 1).max() < 1e-6
+    assert np.abs(np.abs(b.chi(3, 5)) - 1).max() < 1e-12
+
+
+def test_cq_square_lattice_and_pair_counts():
+    """On the square lattice with q = (2 pi / a)(1, 0), q.d is a multiple of
+    2 pi for every pair, so C_q(r) = 1 wherever pairs exist; the pair counts
+    per window agree with a direct count of the lattice distances."""
+    n = 16
+    b, Lq = _square_lattice(n, 0.5)
+    L = Lq * Q
+    a = L / n
+    dr, B = 0.25, 40
+    num, cnt = b.cq(2 * math.pi / a, 0.0, dr, B)
+    assert cnt.sum() > 0
+    ok = cnt > 0
+    assert np.abs(num[ok] / cnt[ok] - 1).max() < 1e-9
+    # direct count: lattice displacement vectors (minimum image)
+    d = []
+    for di in range(-n // 2 + 1, n // 2 + 1):
+        for dj in range(-n // 2 + 1, n // 2 + 1):
+            if di == 0 and dj == 0:
+                continue
+            d.append(a * math.hypot(di, dj))
+    d = np.array(d)
+    ref = np.array([((d >= bb * dr - 1) & (d <= bb * dr + 1)).sum() for bb in range(B)])
+    # every disk sees the same displacements: unordered pairs = N * ref / 2
+    assert np.array_equal(cnt, n * n * ref // 2)
+
+
+def test_cq_two_disks():
+    b = OracleBox(2, 0.04, lattice=2)
+    i = b.info()
+    Lq = i["W"] * i["M"]
+    X = np.array([2 << 22, (2 << 22) + int(3.3 * (1 << 22))], np.int64)
+    Y = np.array([2 << 22, (2 << 22) + int(1.7 * (1 << 22))], np.int64)
+    b.set_positions_q(X, Y)
+    qx, qy = 1.3, -0.4
+    num, cnt = b.cq(qx, qy, 0.5, 10)
+    dx, dy = (X[1] - X[0]) * Q, (Y[1] - Y[0]) * Q
+    r = math.hypot(dx, dy)
+    for bb in range(10):
+        inside = bb * 0.5 - 1 <= r <= bb * 0.5 + 1
+        assert cnt[bb] == (1 if inside else 0)
+        assert abs(num[bb] - (math.cos(qx * dx + qy * dy) if inside else 0.0)) < 1e-12
