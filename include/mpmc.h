@@ -159,6 +159,66 @@ int mpmc_contact_hist_subset(mpmc_box b, const uint8_t *sel, int64_t *counts);
 int mpmc_psi6_field(mpmc_box b, float *re, float *im, float *field_re, float *field_im,
                     double *Psi_re, double *Psi_im, int on_device);
 
+/* Positional order, Sec. IV.D.  Wave vectors are those the periodic box
+ * allows, q = (2 pi / L_eff)(h, k) with integers |h|, |k| < 4096 and
+ * L_eff = M w.  Positions are the exact absolute ones in q units; each phase
+ * (h X + k Y) / (M W) is reduced in fp64 before its sine and cosine. */
+
+/* Structure factor S(q) = |sum_n exp(i q.x_n)|^2 / N (the double sum over
+ * n, m of Sec. IV.D) at nq wave vectors: hk holds (h, k) pairs, S receives
+ * nq values (host arrays).  Each term's sine and cosine are evaluated in fp32
+ * from the fp64-reduced phase and summed in fp64: every term carries an
+ * absolute error below 1e-6, so |dS| <= 2e-6 sqrt(N S) + 1e-12 N.
+ * MPMC_EINVAL for an index outside (-4096, 4096). */
+int mpmc_structure_factor(mpmc_box b, const int32_t *hk, uint32_t nq, double *S);
+
+/* The first diffraction peak: of the allowed wave vectors q != 0 with
+ * q_lo <= |q| <= q_hi and direction atan2(k, h) in [theta0, theta0 + dtheta)
+ * modulo 2 pi (radians; dtheta >= 2 pi means every direction), the one with
+ * the largest S (the first in the order k, then h ascending on ties).
+ * Outputs may be NULL.  MPMC_EINVAL if the window is empty or q_hi reaches
+ * the index limit. */
+int mpmc_find_q0(mpmc_box b, double q_lo, double q_hi, double theta0, double dtheta,
+                 int32_t *h, int32_t *k, double *S);
+
+/* Positional order parameter chi_j = exp(i q0.x_j), q0 = (2 pi / L_eff)(h, k),
+ * by tag into re/im (N floats each, phase reduced exactly in integers and
+ * evaluated in fp64); field_re/field_im: per cell of the current grid
+ * (M*M floats, cell i + M j) the mean chi_j over its 3 x 3 block, the field
+ * chi(x) drawn in Sec. IV.D.  Device pointers when on_device != 0, else
+ * host; any output may be NULL. */
+int mpmc_chi_field(mpmc_box b, int32_t h, int32_t k, float *re, float *im, float *field_re,
+                   float *field_im, int on_device);
+
+/* Positional correlation C_q(r) (Sec. IV.D) for any wave vector (qx, qy) in
+ * 1/sigma, so that each configuration can use its own rotated q0: over the
+ * unordered pairs whose minimum-image separation d (exact in q units)
+ * satisfies r_b - 1 <= |d| <= r_b + 1 with r_b = b dr, b = 0..nbins-1 (the
+ * lower edge clamped at 0), ADDS the sum of cos(q.d) (fp64) to num[b] and the
+ * number of pairs to cnt[b] (host arrays), so that calls over several
+ * configurations accumulate the configuration average; C_q(r_b) =
+ * num[b] / cnt[b].  The window test is exact in 64-bit integers.
+ * MPMC_EINVAL unless dr is a positive multiple of 2^-22, 1 <= nbins <= 4096
+ * and (nbins - 1) dr + 1 < min(L_eff / 2, 512). */
+int mpmc_cq(mpmc_box b, double qx, double qy, double dr, uint32_t nbins, double *num,
+            int64_t *cnt);
+
+/* mpmc_cq with the configuration turned to a reference orientation
+ * (Sec. IV.D): the wave vector (qx, qy) is rotated by
+ * angle = remainder(arg Psi_6 - psi_arg_ref, 2 pi) / 6, Psi_6 the current
+ * global mean of Eq. (8), before the windows are accumulated; *angle (may be
+ * NULL) receives it.  Calling it on successive configurations with the same
+ * reference gives the coherent configuration average.  MPMC_EINVAL if
+ * Psi_6 = 0 or for the arguments mpmc_cq rejects. */
+int mpmc_cq_aligned(mpmc_box b, double qx, double qy, double psi_arg_ref, double dr,
+                    uint32_t nbins, double *num, int64_t *cnt, double *angle);
+
+/* Incoherent averaging (appendix on configuration averaging): out[g] = the
+ * maximum of C[i] over the windows g*width <= i < min((g+1)*width, n), for
+ * g < ceil(n / width); the caller averages these maxima over
+ * configurations.  Host arrays; MPMC_EINVAL if n or width is 0. */
+int mpmc_cq_bin_max(const double *C, uint32_t n, uint32_t width, double *out);
+
 /* Absolute positions by tag: (i w + u + S) mod L_eff in sigma (double) or
  * in q units (int64); either pair may be NULL. */
 int mpmc_get_positions(mpmc_box b, double *x, double *y, int64_t *X, int64_t *Y);

@@ -97,6 +97,17 @@ int Box::alloc_dev(void **ptr, size_t bytes) {
     return MPMC_OK;
 }
 
+void Box::free_dev(void *ptr) {
+    if (!ptr) return;
+    for (size_t i = 0; i < allocations.size(); ++i)
+        if (allocations[i] == ptr) {
+            allocations.erase(allocations.begin() + i);
+            if (p.alloc) p.free(ptr, p.alloc_ctx);
+            else hipFree(ptr);
+            return;
+        }
+}
+
 void Box::release() {
     if (graph_exec) hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;

@@ -63,6 +63,10 @@ struct Box {
     uint32_t *loc = nullptr;   // slot of every disk by tag (measurement kernels)
     int locate();              // fills loc for the current state
     void *meas_work = nullptr;  // partial results of the tiled measurement kernels
+    void *pos_work = nullptr;   // positional-order partials and staging
+    size_t pos_work_bytes = 0;
+    int pos_work_at_least(size_t bytes);  // grows pos_work (contents lost)
+    float *chi_buf = nullptr;   // chi re/im[N], field re/im[M*M]
     int measure_work();         // allocates meas_work on first use
     uint64_t n_conf = 0;
     // blocks for the pressure standard error
@@ -81,6 +85,7 @@ struct Box {
     std::vector<void *> allocations;
 
     int alloc_dev(void **ptr, size_t bytes);
+    void free_dev(void *ptr);  // releases one allocation of alloc_dev
     void release();
     BoxView view(int from) const;
     MeasureView mview() const;

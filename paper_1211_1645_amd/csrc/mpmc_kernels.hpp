@@ -83,4 +83,19 @@ void launch_psi6_field(const MeasureView &m, const float *re, const float *im, f
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);
 void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st);
 
+// Positional order.  Structure factor at nq wave vectors (2 pi / L)(h, k)
+// (device hk[2 nq], S[nq]); work: rho_work_bytes(m, nq) bytes.
+size_t rho_work_bytes(const MeasureView &m, uint32_t nq);
+void launch_structure_factor(const MeasureView &m, const int32_t *hk, uint32_t nq, double *S,
+                             void *work, hipStream_t st);
+// chi_j = exp(i (2 pi / L)(h X_j + k Y_j)) by tag
+void launch_chi(const MeasureView &m, int32_t h, int32_t k, float *re, float *im, hipStream_t st);
+// C_q(r) windows b < B of half-width 1 around b dr (dr a multiple of 2^-22,
+// top = (B - 1) dr + 1 < min(L / 2, 512)), stencil half-width R >= top / w + 1
+// cells; sums over unordered pairs into num[B], cnt[B] (overwritten);
+// work: cq_work_bytes(m, B) bytes.
+size_t cq_work_bytes(const MeasureView &m, uint32_t B);
+void launch_cq(const MeasureView &m, double qx, double qy, double dr, uint32_t B, int R,
+               double top, void *work, double *num, unsigned long long *cnt, hipStream_t st);
+
 }  // namespace mpmc

@@ -456,7 +456,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         const float4 ux = ux_r[i], uy = uy_r[i];
         const uint4 tg = tg_r[i];
         const int exm = ex > 0 ? ex - 1 : 0, eym = ey > 0 ? ey - 1 : 0;
-        const int exp1 = ex < TE - 1 ? ex + 1 : TE - 1, eyp1 = ey < TE - 1 ? ey + 1 : TE - 1;
+        const int exp1 = ex < TE - 1 ? ex + 1 : TE - 1;
         const uint32_t g_l = L.gcnt[exm + TE * ey];     // (ex-1, ey)
         const uint32_t g_d = L.gcnt[ex + TE * eym];     // (ex, ey-1)
         const uint32_t g_dr = L.gcnt[exp1 + TE * eym];  // (ex+1, ey-1)

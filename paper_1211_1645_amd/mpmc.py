@@ -65,6 +65,14 @@ _SIGS = {
     "mpmc_contact_hist_subset": [_P, _P, _P],
     "mpmc_psi6_field": [_P, _P, _P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int],
     "mpmc_get_positions": [_P, _P, _P, _P, _P],
+    "mpmc_structure_factor": [_P, _P, C.c_uint32, _P],
+    "mpmc_find_q0": [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
+                     C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+    "mpmc_chi_field": [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int],
+    "mpmc_cq": [_P, C.c_double, C.c_double, C.c_double, C.c_uint32, _P, _P],
+    "mpmc_cq_aligned": [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32, _P, _P,
+                        C.POINTER(C.c_double)],
+    "mpmc_cq_bin_max": [_P, C.c_uint32, C.c_uint32, _P],
     "mpmc_get_cells": [_P, _P, _P, _P, _P],
     "mpmc_get_info": [_P, C.POINTER(Info)],
     "mpmc_validate": [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
@@ -279,7 +287,6 @@ class Box:
         r, i = C.c_double(), C.c_double()
         if device:
             import torch
-            psi = torch.empty(self.N, 2, dtype=torch.float32, device="cuda")
             re = torch.empty(self.N, dtype=torch.float32, device="cuda")
             im = torch.empty(self.N, dtype=torch.float32, device="cuda")
             fre = torch.empty(self.M * self.M, dtype=torch.float32, device="cuda")
@@ -287,7 +294,6 @@ class Box:
             _check(_lib.mpmc_psi6_field(self.h, C.c_void_p(re.data_ptr()), C.c_void_p(im.data_ptr()),
                                         C.c_void_p(fre.data_ptr()), C.c_void_p(fim.data_ptr()),
                                         C.byref(r), C.byref(i), 1))
-            del psi
             return torch.complex(re, im), torch.complex(fre, fim), complex(r.value, i.value)
         re = np.zeros(self.N, np.float32)
         im = np.zeros(self.N, np.float32)
@@ -303,6 +309,59 @@ class Box:
         r, i = C.c_double(), C.c_double()
         _check(_lib.mpmc_psi6_field(self.h, None, None, None, None, C.byref(r), C.byref(i), 0))
         return complex(r.value, i.value)
+
+    # ---- positional order (Sec. IV.D) --------------------------------------
+    def wave_vector(self, h, k):
+        """(qx, qy) = (2 pi / L_eff)(h, k) in 1/sigma."""
+        u = 2.0 * np.pi / self.info()["L_eff"]
+        return u * h, u * k
+
+    def structure_factor(self, hk):
+        """S(q) at the allowed wave vectors given as integer pairs (h, k)."""
+        hk = np.ascontiguousarray(np.asarray(hk, np.int32).reshape(-1, 2))
+        S = np.zeros(len(hk), np.float64)
+        _check(_lib.mpmc_structure_factor(self.h, _ptr(hk), len(hk), _ptr(S)))
+        return S
+
+    def find_q0(self, q_lo, q_hi, theta0=0.0, dtheta=2.0 * np.pi):
+        """The allowed wave vector of largest S in the window; (h, k, S)."""
+        h, k, S = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.mpmc_find_q0(self.h, q_lo, q_hi, theta0, dtheta, C.byref(h), C.byref(k),
+                                 C.byref(S)))
+        return h.value, k.value, S.value
+
+    def chi_field(self, h, k):
+        """chi_j = exp(i q0.x_j) by tag and its field per cell (3 x 3 mean)."""
+        nc = self.M * self.M
+        re, im = np.zeros(self.N, np.float32), np.zeros(self.N, np.float32)
+        fre, fim = np.zeros(nc, np.float32), np.zeros(nc, np.float32)
+        _check(_lib.mpmc_chi_field(self.h, h, k, _ptr(re), _ptr(im), _ptr(fre), _ptr(fim), 0))
+        return re + 1j * im.astype(np.complex64), fre + 1j * fim.astype(np.complex64)
+
+    def cq(self, qx, qy, dr, nbins, num=None, cnt=None):
+        """Adds this configuration's window sums of cos(q.d) and pair counts
+        into (num, cnt) (new zero arrays when None) and returns them;
+        C_q(r_b) = num / cnt at r_b = b dr."""
+        num = np.zeros(nbins, np.float64) if num is None else num
+        cnt = np.zeros(nbins, np.int64) if cnt is None else cnt
+        assert num.dtype == np.float64 and cnt.dtype == np.int64
+        assert num.flags.c_contiguous and cnt.flags.c_contiguous
+        assert len(num) == nbins and len(cnt) == nbins
+        _check(_lib.mpmc_cq(self.h, qx, qy, dr, nbins, _ptr(num), _ptr(cnt)))
+        return num, cnt
+
+    def cq_aligned(self, qx, qy, psi_arg_ref, dr, nbins, num=None, cnt=None):
+        """cq with q turned by the change of arg Psi_6 / 6 from psi_arg_ref;
+        returns (num, cnt, angle)."""
+        num = np.zeros(nbins, np.float64) if num is None else num
+        cnt = np.zeros(nbins, np.int64) if cnt is None else cnt
+        assert num.dtype == np.float64 and cnt.dtype == np.int64
+        assert num.flags.c_contiguous and cnt.flags.c_contiguous
+        assert len(num) == nbins and len(cnt) == nbins
+        a = C.c_double()
+        _check(_lib.mpmc_cq_aligned(self.h, qx, qy, psi_arg_ref, dr, nbins, _ptr(num), _ptr(cnt),
+                                    C.byref(a)))
+        return num, cnt, a.value
 
     # ---- state ------------------------------------------------------------
     def info(self):
@@ -473,6 +532,15 @@ def sweep_learned(box, learner, k=1, eps=0.1, counts=False):
     _check(load().mpmc_sweep_learned(box.h, learner.h, k, eps, C.byref(t) if counts else None,
                                      C.byref(a) if counts else None))
     return (t.value, a.value) if counts else None
+
+
+def cq_bin_max(Cv, width):
+    """Maxima of C over groups of `width` consecutive windows."""
+    load()
+    Cv = np.ascontiguousarray(Cv, np.float64)
+    out = np.zeros((len(Cv) + width - 1) // width, np.float64)
+    _check(_lib.mpmc_cq_bin_max(_ptr(Cv), len(Cv), width, _ptr(out)))
+    return out
 
 
 def acf(series, maxlag):

@@ -71,6 +71,10 @@ def test_null_handles():
     assert lib.mpmc_sweep(None, 1, None, None) == mpmc.EINVAL
     assert lib.mpmc_measure_pressure(None, None, None, None, None) == mpmc.EINVAL
     assert lib.mpmc_init_box(None, 256, 0.6, 0, None) == mpmc.EINVAL
+    assert lib.mpmc_structure_factor(None, None, 1, None) == mpmc.EINVAL
+    assert lib.mpmc_find_q0(None, 1.0, 2.0, 0.0, 1.0, None, None, None) == mpmc.EINVAL
+    assert lib.mpmc_chi_field(None, 1, 0, None, None, None, None, 0) == mpmc.EINVAL
+    assert lib.mpmc_cq(None, 1.0, 0.0, 0.5, 4, None, None) == mpmc.EINVAL
 
 
 def test_acf_and_tau_on_ar1():
@@ -97,3 +101,15 @@ def test_acf_and_tau_on_ar1():
 def test_tau_rejects_short_window():
     with pytest.raises(mpmc.MPMCError):
         mpmc.tau(np.array([1.0, 0.01, 0.0, 0.0]))
+
+
+def test_cq_bin_max_groups():
+    """Incoherent averaging takes the maximum within groups of windows; the
+    last group may be short."""
+    rng = np.random.default_rng(4)
+    c = rng.normal(size=23)
+    out = mpmc.cq_bin_max(c, 5)
+    want = [c[i:i + 5].max() for i in range(0, 23, 5)]
+    assert np.array_equal(out, want)
+    assert np.array_equal(mpmc.cq_bin_max(c, 1), c)
+    assert mpmc.load().mpmc_cq_bin_max(None, 3, 1, None) == mpmc.EINVAL

@@ -240,6 +240,18 @@ def test_full_size_parity_sampled(gpu_lib):
     opsi = o.psi6(sel)
     idx = np.nonzero(sel)[0]
     assert np.abs(psi[idx] - opsi[idx]).max() < 1e-5
+    # positional order (Sec. IV.D): S at sampled wave vectors, chi sampled
+    hk = np.array([[0, 0], [1, 0], [0, 1024], [-512, 886], [511, -886], [4095, 4095]], np.int32)
+    S, So = g.structure_factor(hk), o.structure_factor(hk)
+    assert np.all(np.abs(S - So) <= 2e-6 * np.sqrt(cfg["N"] * So) + 1e-12 * cfg["N"] + 1e-12)
+    chi, _ = g.chi_field(-512, 886)
+    assert np.abs(chi[idx] - o.chi(-512, 886)[idx]).max() < 1e-6
+    # C_q at any size: at q = 0 every cosine is exactly 1; counts do not
+    # depend on q; no pair is closer than 2 sigma
+    n0, c0 = g.cq(0.0, 0.0, 0.5, 40)
+    n1, c1 = g.cq(*g.wave_vector(-512, 886), 0.5, 40)
+    assert np.array_equal(n0, c0.astype(np.float64)) and np.array_equal(c0, c1)
+    assert c0[:2].sum() == 0 and c0[3] > 0 and np.all(np.abs(n1) <= c1)
     assert g.validate() == (0, 0)
 
 
