@@ -155,6 +155,113 @@ def learned_comparison(seed, minutes_budget=0.5):
     return out
 
 
+# Algorithmic 32-bit operation slots of one structure-factor term (one disk,
+# one wave vector): the fp64 phase h x + k y, its fraction and scaling (5 fp64
+# operations; fp64 vector arithmetic issues at the 32-bit rate on this chip,
+# 78.6 TFLOP/s of fp64 FMA = 256 CUs x 64 lanes x 2.4 GHz x 2), one conversion,
+# sincos of the reduced argument (range reduction and two minimax polynomials
+# in Horner form with the quadrant fix-up: 20), and the two fp64 accumulations
+# with their conversions (4): 30.
+ALU_OPS_RHO_TERM = 30.0
+
+
+def positional_bench(args):
+    """Positional order (Sec. IV.D) on an equilibrating N = 1024^2 box at
+    eta = 0.716: the structure-factor scan for q0, chi_j, and C_q0(r) out to
+    r = 100 sigma."""
+    import math
+    import numpy as np
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular",
+                     stream=stream.cuda_stream)
+        box.sweep(200)
+        info = box.info()
+        L = info["L_eff"]
+        a0 = math.sqrt(2.0 / (math.sqrt(3.0) * info["N"] / L ** 2))
+        qp = 4 * math.pi / (math.sqrt(3.0) * a0)
+        unit = 2 * math.pi / L
+        # one launch worth of wave vectors (65536) in the annulus sector
+        r = int(math.ceil(1.1 * qp / unit))
+        k, h = np.meshgrid(np.arange(-r, r + 1), np.arange(-r, r + 1), indexing="ij")
+        h, k = h.ravel(), k.ravel()
+        n = np.hypot(h, k) * unit
+        ang = np.arctan2(k, h)
+        sel = (n >= 0.9 * qp) & (n <= 1.1 * qp) & (ang >= 0) & (ang < math.pi / 3)
+        hk = np.stack([h[sel], k[sel]], 1)[:65536].astype(np.int32)
+        box.structure_factor(hk[:256])   # warm-up
+        times = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            S = box.structure_factor(hk)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        t_s = sum(times) / len(times)
+        terms = float(len(hk)) * info["N"]
+        t0 = time.perf_counter()
+        hq, kq, Sq = box.find_q0(0.9 * qp, 1.1 * qp, 0.0, math.pi / 3)
+        torch.cuda.synchronize()
+        t_find = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        chi, field = box.chi_field(hq, kq)
+        torch.cuda.synchronize()
+        t_chi = time.perf_counter() - t0
+        qx, qy = unit * hq, unit * kq
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        num, cnt = box.cq(qx, qy, 1.0, 100)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_cq = e0.elapsed_time(e1) * 1e-3
+    achieved = terms * ALU_OPS_RHO_TERM / t_s / 1e12
+    line = {
+        "metric": "structure-factor terms/s (disk x wave vector), 1024^2 disks eta=0.716",
+        "value": terms / t_s,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": t_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 phase, f32 sincos, f64 sums",
+        "data": "synthetic (triangular start, 200 sweeps, Philox4x32-10 seed %d)" % args.seed,
+        "config": {"workload": "positional order: S(q) at %d allowed wave vectors of the "
+                               "annulus sector 0.9-1.1 x 4pi/(sqrt3 a0), 0-60 deg; q0 search "
+                               "over the whole sector; chi_j; C_q0(r) for r = 0..99 sigma"
+                               % len(hk), "N": info["N"], "eta": ETA, "M": info["M"]},
+        "q0": {"h": hq, "k": kq, "S": Sq, "q": math.hypot(qx, qy), "search_s": t_find},
+        "chi_s": t_chi,
+        "cq": {"seconds": t_cq, "bins": 100, "dr": 1.0, "pairs": int(cnt.sum()),
+               "C_at_10_50_99": [float(num[i] / cnt[i]) for i in (10, 50, 99)]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "k_rho (one launch of %d wave vectors)" % len(hk),
+                     "ops_per_term": ALU_OPS_RHO_TERM},
+    }
+    if not args.no_cpu_baseline:
+        from oracle.orc import OracleBox
+        o = OracleBox(N_DISKS, ETA, seed=args.seed, lattice=1, step_m=20)
+        o.sweep(1)
+        t0 = time.perf_counter()
+        o.structure_factor(hk[:8])
+        one = (time.perf_counter() - t0) / 8
+        nq = max(8, min(len(hk), int(15.0 / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        o.structure_factor(hk[:nq])
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(
+            value=nq * float(info["N"]) / dt, unit="terms/s", cores=1, kind="oracle",
+            sample="S(q) at %d of the same wave vectors on the oracle's N=1024^2 box after one "
+                   "sweep (%.1f s, 1 thread)" % (nq, dt))
+    print(json.dumps(line))
+
+
 def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
     """The oracle (single thread) on the same start and step: sweeps of the
     full 1024^2 box until about target_seconds of CPU work."""
@@ -189,6 +296,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--workload", choices=("sweep", "positional"), default="sweep",
+                    help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -203,6 +312,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "positional":
+        positional_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
