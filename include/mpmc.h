@@ -219,6 +219,39 @@ int mpmc_cq_aligned(mpmc_box b, double qx, double qy, double psi_arg_ref, double
  * configurations.  Host arrays; MPMC_EINVAL if n or width is 0. */
 int mpmc_cq_bin_max(const double *C, uint32_t n, uint32_t width, double *out);
 
+/* Equation-of-state loop (Sec. IV.A).  In a finite box P*(eta) near the
+ * transition shows a Mayer-Wood loop; integrating it gives the interface free
+ * energy per disk.  With v = pi / eta the area per disk (sigma the radius) and
+ * beta P sigma^2 = P* / 4:
+ *   - P*(v) is the least-squares polynomial of the given order (3..9) in
+ *     v - mean(v), weighted by 1/se^2 when se != NULL (host arrays of n >=
+ *     order + 2 points);
+ *   - eta_max/p_max: its local maximum (the lower-density extremum), and
+ *     eta_min/p_min: its local minimum, both inside the data range;
+ *   - p_coex: the Maxwell pressure, equal areas of P* - p_coex between the
+ *     outer roots of P* = p_coex, eta_liquid < eta_solid being those roots;
+ *   - delta_f: beta Delta f, a quarter of the area between P* and p_coex from
+ *     the solid root to the middle root (the free energy per disk above the
+ *     common tangent at its largest).
+ * MPMC_EINVAL for bad input; MPMC_ESTATE if the fit has no loop (not exactly
+ * one maximum below the density of exactly one minimum) or the construction
+ * would need data outside the range. */
+typedef struct {
+    double eta_max, p_max, eta_min, p_min;
+    double p_coex, eta_liquid, eta_solid;
+    double delta_f;
+} mpmc_eos_loop_result;
+int mpmc_eos_loop(const double *eta, const double *p_star, const double *se, uint32_t n,
+                  uint32_t order, mpmc_eos_loop_result *out);
+
+/* Finite-size scaling (Sec. IV.A): y = prefactor * x^exponent by least
+ * squares on (ln x, ln y), e.g. Delta f against N, where -1/2 marks a
+ * first-order transition in two dimensions and -1 a continuous one.  Either
+ * output may be NULL; MPMC_EINVAL unless n >= 2, all values positive and the
+ * x not all equal. */
+int mpmc_power_law(const double *x, const double *y, uint32_t n, double *exponent,
+                   double *prefactor);
+
 /* Absolute positions by tag: (i w + u + S) mod L_eff in sigma (double) or
  * in q units (int64); either pair may be NULL. */
 int mpmc_get_positions(mpmc_box b, double *x, double *y, int64_t *X, int64_t *Y);

@@ -40,6 +40,11 @@ class Info(C.Structure):
                 ("accepts", C.c_uint64), ("n_conf", C.c_uint64)]
 
 
+class EosLoop(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("eta_max", "p_max", "eta_min", "p_min", "p_coex",
+                                          "eta_liquid", "eta_solid", "delta_f")]
+
+
 class MPMCError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("MPMC error %d: %s" % (code, msg))
@@ -73,6 +78,8 @@ _SIGS = {
     "mpmc_cq_aligned": [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32, _P, _P,
                         C.POINTER(C.c_double)],
     "mpmc_cq_bin_max": [_P, C.c_uint32, C.c_uint32, _P],
+    "mpmc_eos_loop": [_P, _P, _P, C.c_uint32, C.c_uint32, C.POINTER(EosLoop)],
+    "mpmc_power_law": [_P, _P, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double)],
     "mpmc_get_cells": [_P, _P, _P, _P, _P],
     "mpmc_get_info": [_P, C.POINTER(Info)],
     "mpmc_validate": [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
@@ -541,6 +548,30 @@ def cq_bin_max(Cv, width):
     out = np.zeros((len(Cv) + width - 1) // width, np.float64)
     _check(_lib.mpmc_cq_bin_max(_ptr(Cv), len(Cv), width, _ptr(out)))
     return out
+
+
+def eos_loop(eta, p_star, se=None, order=3):
+    """Mayer-Wood loop analysis of an equation of state (Sec. IV.A): dict of
+    the extrema, Maxwell pressure, coexisting densities and beta Delta f."""
+    load()
+    eta = np.ascontiguousarray(eta, np.float64)
+    p = np.ascontiguousarray(p_star, np.float64)
+    assert eta.shape == p.shape
+    s = None if se is None else np.ascontiguousarray(se, np.float64)
+    r = EosLoop()
+    _check(_lib.mpmc_eos_loop(_ptr(eta), _ptr(p), None if s is None else _ptr(s), len(eta), order,
+                              C.byref(r)))
+    return {f: getattr(r, f) for f, _ in EosLoop._fields_}
+
+
+def power_law(x, y):
+    """(exponent, prefactor) of y = a x^b by least squares on logarithms."""
+    load()
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    b, a = C.c_double(), C.c_double()
+    _check(_lib.mpmc_power_law(_ptr(x), _ptr(y), len(x), C.byref(b), C.byref(a)))
+    return b.value, a.value
 
 
 def acf(series, maxlag):
