@@ -89,6 +89,22 @@ def stored_traffic():
     return d.get("bytes_per_launch")
 
 
+def stored_tau():
+    """The Psi_6 correlation time measured by `--workload tau` at the paper's
+    speed-comparison point (N = 512^2, eta = 0.698), from its committed
+    summary, or None."""
+    path = os.path.join(ROOT, "profiles", "psi6_tau_512sq_eta0698.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    keys = ("tau_efold_displacements_per_disk", "tau_displacements_per_disk",
+            "paper_tau_displacements_per_disk", "decorrelations_per_s", "sweeps_per_s",
+            "command")
+    out = {k: d.get(k) for k in keys}
+    out["N"], out["eta"], out["source"] = 512 * 512, 0.698, "profiles/psi6_tau_512sq_eta0698.json"
+    return out
+
+
 def copy_calibration(nbytes=512 << 20, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -155,14 +171,15 @@ def learned_comparison(seed, minutes_budget=0.5):
     return out
 
 
-# Algorithmic 32-bit operation slots of one structure-factor term (one disk,
-# one wave vector): the fp64 phase h x + k y, its fraction and scaling (5 fp64
-# operations; fp64 vector arithmetic issues at the 32-bit rate on this chip,
-# 78.6 TFLOP/s of fp64 FMA = 256 CUs x 64 lanes x 2.4 GHz x 2), one conversion,
-# sincos of the reduced argument (range reduction and two minimax polynomials
-# in Horner form with the quadrant fix-up: 20), and the two fp64 accumulations
-# with their conversions (4): 30.
-ALU_OPS_RHO_TERM = 30.0
+# Algorithmic operations of one structure-factor term (one disk, one wave
+# vector) as k_rho evaluates it (fp64 vector arithmetic issues at the 32-bit
+# rate on this chip: 78.6 TFLOP/s of fp64 FMA = 256 CUs x 64 lanes x 2.4 GHz
+# x 2): the scaled phase h x + k y (2 fp64), its integer part and fraction
+# (2), conversion and scaling of the fraction (2), the table index (2), the
+# table read (1), the squared residual angle (1), its cosine and sine from the
+# Taylor series (5), the rotation by the table entry (4) and the two fp64
+# accumulations with their conversions (4): 23.
+ALU_OPS_RHO_TERM = 23.0
 
 
 def positional_bench(args):
@@ -229,7 +246,7 @@ def positional_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 phase, f32 sincos, f64 sums",
+        "dtype": "f64 phase, f32 rotation, f64 sums",
         "data": "synthetic (triangular start, 200 sweeps, Philox4x32-10 seed %d)" % args.seed,
         "config": {"workload": "positional order: S(q) at %d allowed wave vectors of the "
                                "annulus sector 0.9-1.1 x 4pi/(sqrt3 a0), 0-60 deg; q0 search "
@@ -259,6 +276,108 @@ def positional_bench(args):
             value=nq * float(info["N"]) / dt, unit="terms/s", cores=1, kind="oracle",
             sample="S(q) at %d of the same wave vectors on the oracle's N=1024^2 box after one "
                    "sweep (%.1f s, 1 thread)" % (nq, dt))
+    print(json.dumps(line))
+
+
+TAU_N, TAU_ETA = 512 * 512, 0.698
+TAU_PAPER_DISP = 8.0e5   # MPMC correlation time of Psi_6 in displacements per disk (Table II)
+
+
+def tau_analysis(series, sample, disp_per_sweep, discard):
+    """tau of a Psi_6 series sampled every `sample` sweeps: the exponential
+    fit of Sec. III over 0.05 <= C <= 0.5, the e-folding lag (first C < 1/e,
+    the larger and so the conservative figure for runs of a few tens of tau,
+    which the decorrelation rate uses) and the integrated time, for the whole
+    series after
+    `discard` sweeps and for its two halves, in displacements per disk."""
+    import math
+    import numpy as np
+    import paper_1211_1645_amd.mpmc as mp
+    x = np.asarray(series)[discard // sample:]
+    unit = sample * disp_per_sweep
+
+    def one(part):
+        Cv = mp.acf(part, len(part) // 4)
+        try:
+            t, ti = mp.tau(Cv, 0.05, 0.5)
+        except mp.MPMCError:   # too short for the exponential tail
+            t, ti = float("nan"), float("nan")
+        below = np.nonzero(Cv < math.exp(-1.0))[0]
+        ef = float(below[0]) if len(below) else float("nan")
+        return t * unit, ef * unit, ti * unit
+
+    t, ef, ti = one(x)
+    halves = [one(x[:len(x) // 2]), one(x[len(x) // 2:])]
+    return {"tau_sweeps": t * sample / unit, "tau_displacements_per_disk": t,
+            "tau_efold_displacements_per_disk": ef, "tau_int_displacements_per_disk": ti,
+            "tau_halves_displacements_per_disk": [h[0] for h in halves],
+            "tau_efold_halves_displacements_per_disk": [h[1] for h in halves],
+            "run_length_in_tau": len(x) * unit / t if t == t else None,
+            "abs_Psi6_mean": float(np.abs(x).mean())}
+
+
+def tau_bench(args):
+    """Psi_6 correlation time of the plain sampler at the configuration of the
+    paper's speed comparison (N = 512^2, eta = 0.698, Table II): a long run
+    from the triangular start, Psi_6 every `sample` sweeps (one graph replay
+    each), the first `discard` sweeps dropped, C(dt) of Eq. (9) over all time
+    origins, tau from the exponential tail (Sec. III)."""
+    import numpy as np
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    sample = args.tau_sample
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        box = mp.Box(TAU_N, TAU_ETA, seed=args.seed, step_m=20, lattice="triangular",
+                     stream=stream.cuda_stream)
+        box.set_graphs(sample)
+        step_m, acc = tune_step(box)
+        info = box.info()
+        progress("tau run: N=%d eta=%.3f m=%d schedule %d tile %d" %
+                 (info["N"], TAU_ETA, step_m, info["schedule"], info["tile"]))
+        n_samples = args.tau_sweeps // sample
+        series = np.zeros(n_samples, np.complex128)
+        i0 = box.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = t0
+        for k in range(n_samples):
+            box.sweep(sample)
+            series[k] = box.psi6()
+            now = time.perf_counter()
+            if now - last > 30.0:
+                progress("tau run: %d of %d sweeps, |Psi6| = %.3f" %
+                         ((k + 1) * sample, n_samples * sample, abs(series[k])))
+                last = now
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        i1 = box.info()
+    if args.tau_series:
+        np.save(args.tau_series, series)
+    disp_per_sweep = (i1["trials"] - i0["trials"]) / (n_samples * sample) / info["N"]
+    res = tau_analysis(series, sample, disp_per_sweep, args.tau_discard)
+    sweeps_per_s = n_samples * sample / elapsed
+    line = {
+        "metric": "psi6-decorrelation sweeps/s (sweeps/s / tau), 512^2 disks eta=0.698",
+        "value": sweeps_per_s * disp_per_sweep / res["tau_efold_displacements_per_disk"],
+        "unit": "decorrelations/s",
+        "n_gpus": 1, "steps": n_samples, "warmup": 0,
+        "ms_per_step": elapsed / n_samples * 1e3,
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (triangular start, Philox4x32-10 seed %d)" % args.seed,
+        "config": {"workload": "plain MPMC at the paper's speed-comparison point, N=512^2, "
+                               "eta=0.698, step tuned to ~30%% acceptance (m=%d); %d sweeps, "
+                               "Psi6 every %d, first %d discarded" %
+                               (step_m, n_samples * sample, sample, args.tau_discard),
+                   "N": info["N"], "eta": TAU_ETA, "M": info["M"], "tile": info["tile"]},
+        "sweeps_per_s": sweeps_per_s,
+        "trial_moves_per_s": (i1["trials"] - i0["trials"]) / elapsed,
+        "displacements_per_disk_per_sweep": disp_per_sweep,
+        "tau_sweeps": res["tau_sweeps"],
+        "paper_tau_displacements_per_disk": TAU_PAPER_DISP,
+    }
+    line.update(res)
     print(json.dumps(line))
 
 
@@ -296,8 +415,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "positional"), default="sweep",
-                    help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r)")
+    ap.add_argument("--workload", choices=("sweep", "positional", "tau"), default="sweep",
+                    help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
+                         "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes)")
+    ap.add_argument("--tau-sweeps", type=int, default=20000000)
+    ap.add_argument("--tau-discard", type=int, default=4000000)
+    ap.add_argument("--tau-sample", type=int, default=1000)
+    ap.add_argument("--tau-series", default="", help="save the Psi6 series (.npy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -315,6 +439,9 @@ def main():
         return
     if args.workload == "positional":
         positional_bench(args)
+        return
+    if args.workload == "tau":
+        tau_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -386,6 +513,7 @@ def main():
         "acceptance": accepts / max(trials, 1),
         "trials_per_sweep": trials_per_sweep,
         "psi6_decorrelations_per_s": None,
+        "psi6_tau_at_paper_point": stored_tau(),
         "P_star_sample": pressure["P_star"],
         "abs_Psi6_mean": sum(abs(p) for p in psi_series) / len(psi_series),
         "validate": {"overlaps": overlaps, "bad": bad},

@@ -162,13 +162,15 @@ int mpmc_psi6_field(mpmc_box b, float *re, float *im, float *field_re, float *fi
 /* Positional order, Sec. IV.D.  Wave vectors are those the periodic box
  * allows, q = (2 pi / L_eff)(h, k) with integers |h|, |k| < 4096 and
  * L_eff = M w.  Positions are the exact absolute ones in q units; each phase
- * (h X + k Y) / (M W) is reduced in fp64 before its sine and cosine. */
+ * (h X + k Y) / (M W) is formed in fp64 (structure factor) or reduced
+ * exactly in integers (chi) before its sine and cosine. */
 
 /* Structure factor S(q) = |sum_n exp(i q.x_n)|^2 / N (the double sum over
  * n, m of Sec. IV.D) at nq wave vectors: hk holds (h, k) pairs, S receives
- * nq values (host arrays).  Each term's sine and cosine are evaluated in fp32
- * from the fp64-reduced phase and summed in fp64: every term carries an
- * absolute error below 1e-6, so |dS| <= 2e-6 sqrt(N S) + 1e-12 N.
+ * nq values (host arrays).  Each term exp(i q.x) is an fp32 root of unity
+ * from a 256-entry table, chosen by the fp64 phase, rotated by the residual
+ * angle in fp32, and summed in fp64: every term carries an absolute error
+ * below 1e-6, so |dS| <= 2e-6 sqrt(N S) + 1e-12 N.
  * MPMC_EINVAL for an index outside (-4096, 4096). */
 int mpmc_structure_factor(mpmc_box b, const int32_t *hk, uint32_t nq, double *S);
 

@@ -31,41 +31,61 @@ __device__ __forceinline__ void abs_q(const MeasureView &m, uint32_t c, uint32_t
 // ---------------------------------------------------------------------------
 // rho(q) = sum_n exp(2 pi i (h X_n + k Y_n) / Lq) for kQC wave vectors per
 // workgroup column (blockIdx.y); the gridDim.x workgroups of a column split
-// the cells, each thread serving cells c, c + stride, ...  The phase fraction
-// is formed in fp64 from X / Lq (error below 2^-40 for |h|, |k| < 2^12),
-// rounded once to fp32 and evaluated by sincospif; the terms are summed in
-// fp64, so each term carries an absolute error below 1e-6.  Each workgroup
+// the cells, each thread serving cells c, c + stride, ...
+//
+// Each term: the phase in turns, scaled by 256, t = 256 (h X + k Y) / Lq, is
+// formed in fp64 (|t| < 2^22, error below 2^-30) and split into its integer
+// part i and fraction r; exp(2 pi i t / 256) = T[i mod 256] exp(2 pi i r / 256)
+// with T a table of fp32 roots of unity and the second factor from its
+// Taylor series to fifth order (|angle| < 2 pi / 256: truncation below
+// 1e-12).  The product is formed in fp32 with fused multiply-adds and summed
+// in fp64: every term carries an absolute error below 5e-7.  Each workgroup
 // leaves its kQC partial sums in part[(by * gridDim.x + bx) * kQC + j].
 __global__ void __launch_bounds__(256) k_rho(MeasureView m, const int32_t *hk, uint32_t nq,
                                              double2 *part) {
     __shared__ double2 wsum[4][kQC];
+    __shared__ float2 roots[256];
+    {
+        double sn, cs;
+        sincospi((double)threadIdx.x / 128.0, &sn, &cs);
+        roots[threadIdx.x] = make_float2((float)cs, (float)sn);
+    }
+    __syncthreads();
     const uint32_t NC = m.M * m.M;
     const uint32_t q0 = blockIdx.y * kQC;
-    float fh[kQC], fk[kQC];
+    double fh[kQC], fk[kQC];
     double re[kQC], im[kQC];
 #pragma unroll
     for (int j = 0; j < kQC; ++j) {
         const uint32_t iq = q0 + j < nq ? q0 + j : nq - 1;
-        fh[j] = (float)hk[2 * iq];
-        fk[j] = (float)hk[2 * iq + 1];
+        fh[j] = 256.0 * (double)hk[2 * iq];
+        fk[j] = 256.0 * (double)hk[2 * iq + 1];
         re[j] = im[j] = 0.0;
     }
     const double inv = 1.0 / (double)m.Lq;
+    const float turn = 6.283185307179586f / 256.0f;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < NC; c += stride) {
         const uint32_t n = m.cnt[c];
         for (uint32_t s = 0; s < n; ++s) {
-            long long X, Y;
-            abs_q(m, c, s, &X, &Y);
+            // the position in q units without its reduction modulo Lq (a
+            // whole period more leaves every phase unchanged): below 2 Lq
+            const long long X = (long long)(c % m.M) * m.W +
+                                (long long)(m.x[slot_at(c, s, NC)] * 4194304.0f) + m.Sx;
+            const long long Y = (long long)(c / m.M) * m.W +
+                                (long long)(m.y[slot_at(c, s, NC)] * 4194304.0f) + m.Sy;
             const double xh = (double)X * inv, yh = (double)Y * inv;
 #pragma unroll
             for (int j = 0; j < kQC; ++j) {
-                const double t = (double)fh[j] * xh + (double)fk[j] * yh;
-                const float f = (float)(2.0 * (t - floor(t)));  // phase / pi in [0, 2]
-                float sn, cs;
-                sincospif(f, &sn, &cs);
-                re[j] += cs;
-                im[j] += sn;
+                const double t = fma(fh[j], xh, fk[j] * yh);
+                const double i = floor(t);
+                const float a = (float)(t - i) * turn;  // residual angle in [0, 2 pi / 256]
+                const float2 T = roots[(int)i & 255];
+                const float a2 = a * a;
+                const float cr = fmaf(a2, fmaf(a2, 1.0f / 24.0f, -0.5f), 1.0f);
+                const float sr = a * fmaf(a2, fmaf(a2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+                re[j] += (double)fmaf(T.x, cr, -T.y * sr);
+                im[j] += (double)fmaf(T.y, cr, T.x * sr);
             }
         }
     }

@@ -2,8 +2,8 @@
 states that both sides reach by the same bit-exact trajectory.
 
 Tolerances follow from the arithmetic: the GPU evaluates each term of the
-structure factor in fp32 from an fp64-reduced phase (absolute error below
-1e-6 per term), so |dS| <= 2e-6 sqrt(N S) + 1e-12 N; chi_j is returned in
+structure factor as an fp32 table root of unity rotated by an fp32 residual
+angle from the fp64 phase (absolute error below 1e-6 per term), so |dS| <= 2e-6 sqrt(N S) + 1e-12 N; chi_j is returned in
 fp32 (error below 1e-6); C_q sums fp64 cosines in another order
 (|d num| <= 1e-12 per pair) and its pair counts are exact.
 """
