@@ -180,6 +180,79 @@ __device__ inline void mlp_forward_wave(const WT &W, const FwdBufs &B) {
     wave_sync();
 }
 
+// Inference for one wave's 64 samples with the activations in registers.
+// Each layer forms the transposed product H^T = W X^T (weights as the A
+// operand, samples as the 16 columns of an MFMA tile): the lanes then hold
+// accumulator rows 4(l/16)..+3 of column l%16, which is exactly how the next
+// layer's B operand is laid out, so between layers the activations only pass
+// through the bias, SiLU and the rounding to bf16 in place.  Only the input
+// rows X (bf16 [64][32]) and the outputs OUT (fp32 [64][32], the 20 used in
+// columns 0..19) go through LDS; OUT must not overlap X.
+__device__ inline float silu_fast(float v) {
+    return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
+}
+
+__device__ inline v4s act_bf16(v4f c, const float *bias, int n0) {
+    v4s r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = (short)f2bf(silu_fast(c[e] + bias[n0 + e]));
+    return r;
+}
+
+template <class WT>
+__device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT) {
+    const int l = threadIdx.x & 63, r = l & 15, kg = (l >> 4) * 4;
+#pragma unroll 1
+    for (int mt = 0; mt < 4; ++mt) {
+        v4f c1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) c1[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const v4s b = *reinterpret_cast<const v4s *>(X + (16 * mt + r) * 32 + 16 * ks + kg);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const v4s a = *reinterpret_cast<const v4s *>(W.w1 + (16 * nt + r) * 32 + 16 * ks + kg);
+                c1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c1[nt], 0, 0, 0);
+            }
+        }
+        v4s h1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) h1[nt] = act_bf16(c1[nt], W.b1, 16 * nt + kg);
+        v4f c2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) c2[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const v4s a = *reinterpret_cast<const v4s *>(W.w2 + (16 * nt + r) * 64 + 16 * ks + kg);
+                c2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[ks], c2[nt], 0, 0, 0);
+            }
+        v4s h2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) h2[nt] = act_bf16(c2[nt], W.b2, 16 * nt + kg);
+        v4f c3[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) c3[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const v4s a = *reinterpret_cast<const v4s *>(W.w3 + (16 * nt + r) * 64 + 16 * ks + kg);
+                c3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h2[ks], c3[nt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n = 16 * nt + kg + e;
+                OUT[(16 * mt + r) * 32 + n] = c3[nt][e] + W.b3[n];
+            }
+    }
+    wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // Mixture density and sampling (one lane, one sample).
 struct Gmm {
@@ -234,59 +307,126 @@ __device__ inline float log_q(const Gmm &g, float dx, float dy, int Dx, int Dy, 
 }
 
 // ---------------------------------------------------------------------------
-// Features of a disk of cell (ci, cj) at cell-local (x, y), slot `self` of
-// the own cell excluded, from the slot-major cell lists (cnt, px, py).
-// scr: this lane's 36-float scratch.  Writes bf16 into Xrow[0..31] and/or
-// fp32 into Frow[0..23] (either may be NULL).  Returns the neighbour count.
+// The disks of the 3 x 3 cell block around cell (ci, cj) (M >= 4, so the nine
+// cells are distinct and the own cell is k = 4, k = 3 (dj + 1) + di + 1):
+// the nine counts (3 bits each) and slots 0 and 1 are loaded together, one
+// round trip; slots 2 and 3 are read from the lists where a count asks.
+struct Nbhd {
+    uint32_t m;           // count of cell k in bits 3k..3k+2
+    float x[9][2], y[9][2];
+    uint32_t ci, cj, M;
+};
+
+__device__ inline uint32_t nbhd_cell(const Nbhd &N, int k) {
+    const uint32_t i = (uint32_t)((int)N.ci + k % 3 - 1 + (int)N.M) % N.M;
+    const uint32_t j = (uint32_t)((int)N.cj + k / 3 - 1 + (int)N.M) % N.M;
+    return i + N.M * j;
+}
+
+__device__ inline void load_nbhd(const uint8_t *cnt, const float *px, const float *py,
+                                 uint32_t M, uint32_t ci, uint32_t cj, Nbhd &N) {
+    N.ci = ci;
+    N.cj = cj;
+    N.M = M;
+    N.m = 0;
+    const uint32_t NC = M * M;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t nb = nbhd_cell(N, k);
+        N.m |= (uint32_t)cnt[nb] << (3 * k);
+        N.x[k][0] = px[nb];
+        N.x[k][1] = px[NC + nb];
+        N.y[k][0] = py[nb];
+        N.y[k][1] = py[NC + nb];
+    }
+}
+
+// Calls f(dx, dy) for every disk of the block but slot `self` of the own
+// cell, in the order of cells k, then slots, with (dx, dy) its separation
+// from the point (x, y) of the own cell (each cell's offset c w added last).
+template <class F>
+__device__ inline void for_each_other(const Nbhd &N, const float *px, const float *py, float w,
+                                      uint32_t self, float x, float y, F &&f) {
+    const uint32_t NC = N.M * N.M;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float cwx = (float)(k % 3 - 1) * w, cwy = (float)(k / 3 - 1) * w;
+        const uint32_t m = (N.m >> (3 * k)) & 7u;
+#pragma unroll
+        for (uint32_t s = 0; s < 2; ++s)
+            if (s < m && !(k == 4 && s == self)) f((N.x[k][s] - x) + cwx, (N.y[k][s] - y) + cwy);
+        if (m > 2) {  // rare: slots 2 and 3 from the lists
+            const uint32_t nb = nbhd_cell(N, k);
+            for (uint32_t s = 2; s < m; ++s)
+                if (!(k == 4 && s == self))
+                    f((px[slot_at(nb, s, NC)] - x) + cwx, (py[slot_at(nb, s, NC)] - y) + cwy);
+        }
+    }
+}
+
+// A 32-entry bf16 input row (64 bytes, 16-byte aligned) set to zero.
+__device__ inline void zero_row(uint16_t *row) {
+    uint4 *r = reinterpret_cast<uint4 *>(row);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Features of the disk in slot `self` of the block's own cell at cell-local
+// (x, y).  scr: this lane's 36-float scratch.  Writes bf16 into Xrow[0..31]
+// and/or fp32 into Frow[0..23] (either may be NULL).  Returns the neighbour
+// count.
+__device__ inline int lane_features(const Nbhd &N, const float *px, const float *py, float w,
+                                    uint32_t self, float x, float y, float *scr, uint16_t *Xrow,
+                                    float *Frow) {
+    int n = 0;
+    for_each_other(N, px, py, w, self, x, y, [&](float dx, float dy) {
+        const float r2 = r2_f32(dx, dy);
+        if (!(r2 < 9.0f)) return;
+        if (n < 12) {
+            scr[3 * n] = dx;
+            scr[3 * n + 1] = dy;
+            scr[3 * n + 2] = r2;
+        }
+        ++n;
+    });
+    const int nn = n < 12 ? n : 12;
+    // ranks by (r^2, order found), all twelve squared distances read at once
+    // and compared in registers (entries from nn on are not used)
+    float r2v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r2v[c] = scr[3 * c + 2];
+    if (Xrow) zero_row(Xrow);
+    if (Frow)
+        for (int k = 0; k < 24; ++k) Frow[k] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        if (c < nn) {
+            int rank = 0;
+#pragma unroll
+            for (int e = 0; e < 12; ++e)
+                rank += (e < nn && (r2v[e] < r2v[c] || (r2v[e] == r2v[c] && e < c))) ? 1 : 0;
+            const float dx = scr[3 * c], dy = scr[3 * c + 1];
+            if (Xrow) {
+                Xrow[2 * rank] = f2bf(dx);
+                Xrow[2 * rank + 1] = f2bf(dy);
+            }
+            if (Frow) {
+                Frow[2 * rank] = dx;
+                Frow[2 * rank + 1] = dy;
+            }
+        }
+    }
+    return n;
+}
+
+// The same from the cell lists directly, for a disk of cell (ci, cj).
 __device__ inline int lane_features(const uint8_t *cnt, const float *px, const float *py,
                                     uint32_t M, float w, uint32_t ci, uint32_t cj,
                                     uint32_t self, float x, float y, float *scr, uint16_t *Xrow,
                                     float *Frow) {
-    int n = 0;
-    const uint32_t own = ci + M * cj;
-    for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-            const uint32_t i = (uint32_t)((int)ci + di + (int)M) % M;
-            const uint32_t j = (uint32_t)((int)cj + dj + (int)M) % M;
-            const uint32_t nb = i + M * j;
-            const float cwx = (float)di * w, cwy = (float)dj * w;
-            const uint32_t m = cnt[nb];
-            for (uint32_t s = 0; s < m; ++s) {
-                if (nb == own && s == self) continue;
-                const float dx = (px[slot_at(nb, s, M * M)] - x) + cwx;
-                const float dy = (py[slot_at(nb, s, M * M)] - y) + cwy;
-                const float r2 = r2_f32(dx, dy);
-                if (!(r2 < 9.0f)) continue;
-                if (n < 12) {
-                    scr[3 * n] = dx;
-                    scr[3 * n + 1] = dy;
-                    scr[3 * n + 2] = r2;
-                }
-                ++n;
-            }
-        }
-    const int nn = n < 12 ? n : 12;
-    if (Xrow)
-        for (int k = 0; k < 32; ++k) Xrow[k] = 0;
-    if (Frow)
-        for (int k = 0; k < 24; ++k) Frow[k] = 0.0f;
-    for (int c = 0; c < nn; ++c) {
-        const float rc = scr[3 * c + 2];
-        int rank = 0;
-        for (int e = 0; e < nn; ++e) {
-            const float re = scr[3 * e + 2];
-            rank += (re < rc || (re == rc && e < c)) ? 1 : 0;
-        }
-        if (Xrow) {
-            Xrow[2 * rank] = f2bf(scr[3 * c]);
-            Xrow[2 * rank + 1] = f2bf(scr[3 * c + 1]);
-        }
-        if (Frow) {
-            Frow[2 * rank] = scr[3 * c];
-            Frow[2 * rank + 1] = scr[3 * c + 1];
-        }
-    }
-    return n;
+    Nbhd N;
+    load_nbhd(cnt, px, py, M, ci, cj, N);
+    return lane_features(N, px, py, w, self, x, y, scr, Xrow, Frow);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,30 +438,40 @@ struct LearnView {
     unsigned long long *nfeat_over;  // neighbourhoods with more than 12 disks
 };
 
+constexpr int kLearnWaves = 4;  // waves per workgroup of the learned pass
+
 struct LdsLearn {
-    PackedWInfer w;
-    uint16_t X[64 * 32];
-    uint16_t H1[64 * 64];  // also the network output [64][32] fp32 and,
-    uint16_t H2[64 * 64];  // before the network runs, the feature scratch
+    PackedWInfer w;  // shared by the workgroup's waves
+    struct Wave {
+        uint16_t X[64 * 32];  // network input rows
+        float so[64 * 36];    // feature scratch, then the network output [64][32]
+    } pw[kLearnWaves];
 };
 
-__global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, LearnView lv) {
+// Copies the inference weights into LDS with all threads of the workgroup.
+__device__ inline void load_infer_weights(PackedWInfer &dstw, const PackedW *W, int tid,
+                                          int nthreads) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(W);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&dstw);
+    constexpr uint32_t nw = (64 * 32 + 64 * 64 + 32 * 64) / 2;  // w1, w2, w3 words
+    for (uint32_t k = tid; k < nw; k += nthreads) dst[k] = src[k];
+    for (int k = tid; k < 64; k += nthreads) {
+        dstw.b1[k] = W->b1[k];
+        dstw.b2[k] = W->b2[k];
+        if (k < 32) dstw.b3[k] = W->b3[k];
+    }
+}
+
+__global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, uint32_t pass,
+                                                                   LearnView lv) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     LdsLearn &L = *reinterpret_cast<LdsLearn *>(lds_raw);
-    const int lane = threadIdx.x;
-    // weights into LDS
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(lv.W);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.w);
-        constexpr uint32_t nw = (64 * 32 + 64 * 64 + 32 * 64) / 2;  // w1, w2, w3 words
-        for (uint32_t k = lane; k < nw; k += 64) dst[k] = src[k];
-        L.w.b1[lane] = lv.W->b1[lane];
-        L.w.b2[lane] = lv.W->b2[lane];
-        if (lane < 32) L.w.b3[lane] = lv.W->b3[lane];
-    }
+    const int lane = threadIdx.x & 63;
+    LdsLearn::Wave &P = L.pw[threadIdx.x >> 6];
+    load_infer_weights(L.w, lv.W, threadIdx.x, 64 * kLearnWaves);
     __syncthreads();
     const uint32_t M = v.M, h = M / 2;
-    const uint32_t t = blockIdx.x * 64 + lane;
+    const uint32_t t = blockIdx.x * (64 * kLearnWaves) + threadIdx.x;
     const uint64_t sweep = v.dev->sweep + v.offset;
     const SweepDraws sd = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
     const uint32_t colour = colour_of_pass(sd.perm, pass);
@@ -332,7 +482,7 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
     const uint32_t n = valid ? v.cnt_out[cell] : 0;
     const int Dm = (int)v.step_m << 14;  // d in q units
     const float log_u = -2.0f * logf((float)(2 * Dm + 1) * kQ);
-    float *scr = reinterpret_cast<float *>(L.H1) + 36 * lane;  // scratch before the MLP
+    float *scr = P.so + 36 * lane;  // scratch before the MLP
     uint32_t trials = 0, accepts = 0;
     uint32_t perm = 0x76543210u;
     if (n > 1 && v.n_trial > 1) {
@@ -362,19 +512,22 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
             x = v.x_out[slot_at(cell, slot, M * M)];
             y = v.y_out[slot_at(cell, slot, M * M)];
         }
+        // the neighbourhood is frozen during the trial: loaded once for the
+        // forward features, the overlap test and the reverse features
+        Nbhd nbh;
+        if (act) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
         wave_sync();
         // sorted features into this lane's row of X
         if (act) {
-            const int nf = lane_features(v.cnt_out, v.x_out, v.y_out, M, v.w, ci, cj, slot, x, y,
-                                         scr, L.X + 32 * lane, nullptr);
+            const int nf = lane_features(nbh, v.x_out, v.y_out, v.w, slot, x, y, scr,
+                                         P.X + 32 * lane, nullptr);
             if (nf > 12) atomicAdd(lv.nfeat_over, 1ull);
         } else {
-            for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = 0;
+            zero_row(P.X + 32 * lane);
         }
         wave_sync();
-        float *OUT = reinterpret_cast<float *>(L.H1);
-        FwdBufs fb{L.X, L.H1, L.H2, nullptr, nullptr, nullptr, nullptr, nullptr, OUT};
-        mlp_forward_wave(L.w, fb);
+        float *OUT = P.so;
+        mlp_infer_wave(L.w, P.X, OUT);
         // propose
         Gmm g = gmm_from(OUT + 32 * lane);
         const uint32_t eps_u = (uint32_t)fminf(lv.eps * 4294967296.0f, 4294967295.0f);
@@ -411,32 +564,18 @@ __global__ void __launch_bounds__(64) k_pass_learned(BoxView v, uint32_t pass, L
         const int U = (int)(x * 4194304.0f) + Dx, V = (int)(y * 4194304.0f) + Dy;
         bool ok = act && drawn && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
         const float xn = (float)U * kQ, yn = (float)V * kQ;
-        if (ok) {
-            for (int dj = -1; dj <= 1 && ok; ++dj)
-                for (int di = -1; di <= 1 && ok; ++di) {
-                    const uint32_t i = (uint32_t)((int)ci + di + (int)M) % M;
-                    const uint32_t j = (uint32_t)((int)cj + dj + (int)M) % M;
-                    const uint32_t nb = i + M * j;
-                    const float cwx = (float)di * v.w, cwy = (float)dj * v.w;
-                    const uint32_t m = v.cnt_out[nb];
-                    for (uint32_t s = 0; s < m; ++s) {
-                        if (nb == cell && s == slot) continue;
-                        const float ddx = (v.x_out[slot_at(nb, s, M * M)] - xn) + cwx;
-                        const float ddy = (v.y_out[slot_at(nb, s, M * M)] - yn) + cwy;
-                        if (overlap_f32(ddx, ddy)) { ok = false; break; }
-                    }
-                }
-        }
+        if (ok)
+            for_each_other(nbh, v.x_out, v.y_out, v.w, slot, xn, yn,
+                           [&](float ddx, float ddy) { ok = ok && !overlap_f32(ddx, ddy); });
         // reverse density at x' (every lane takes part in the wave GEMMs)
         wave_sync();
         if (ok) {
-            lane_features(v.cnt_out, v.x_out, v.y_out, M, v.w, ci, cj, slot, xn, yn, scr,
-                          L.X + 32 * lane, nullptr);
+            lane_features(nbh, v.x_out, v.y_out, v.w, slot, xn, yn, scr, P.X + 32 * lane, nullptr);
         } else {
-            for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = 0;
+            zero_row(P.X + 32 * lane);
         }
         wave_sync();
-        mlp_forward_wave(L.w, fb);
+        mlp_infer_wave(L.w, P.X, OUT);
         if (act) ++trials;
         if (ok) {
             const Gmm gr = gmm_from(OUT + 32 * lane);
@@ -732,21 +871,23 @@ __global__ void __launch_bounds__(64) k_train(TrainView tv) {
 }
 
 // Forward only, for given features (diagnostic): out[B][20].
+// It runs the sampler's inference path (mlp_infer_wave).
+struct LdsForward {
+    PackedWInfer w;
+    uint16_t X[64 * 32];
+    float OUT[64 * 32];
+};
+
 __global__ void __launch_bounds__(64) k_forward(const PackedW *W, const float *F, uint32_t B,
                                                 float *out) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    LdsTrain &L = *reinterpret_cast<LdsTrain *>(lds_raw);
+    LdsForward &L = *reinterpret_cast<LdsForward *>(lds_raw);
     const int lane = threadIdx.x;
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(W);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&L.w);
-        for (uint32_t k = lane; k < sizeof(PackedW) / 4; k += 64) dst[k] = src[k];
-    }
+    load_infer_weights(L.w, W, lane, 64);
     const uint32_t s = blockIdx.x * 64 + lane;
     for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = (s < B && k < 24) ? f2bf(F[(size_t)s * 24 + k]) : 0;
     __syncthreads();
-    FwdBufs fb{L.X, L.H1, L.H2, nullptr, nullptr, nullptr, nullptr, nullptr, L.OUT};
-    mlp_forward_wave(L.w, fb);
+    mlp_infer_wave(L.w, L.X, L.OUT);
     if (s < B)
         for (int k = 0; k < 20; ++k) out[(size_t)s * 20 + k] = L.OUT[32 * lane + k];
 }
@@ -1007,7 +1148,7 @@ extern "C" int mpmc_learner_forward(mpmc_learner lh, const float *F, uint32_t B,
     HIPCHK(hipMalloc((void **)&dF, (size_t)B * 24 * 4));
     hipError_t e = hipMalloc((void **)&dO, (size_t)B * 20 * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(dF, F, (size_t)B * 24 * 4, hipMemcpyHostToDevice, l->stream);
-    const size_t lds = sizeof(LdsTrain);
+    const size_t lds = sizeof(LdsForward);
     if (e == hipSuccess) {
         e = hipFuncSetAttribute((const void *)k_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_forward<<<(B + 63) / 64, 64, lds, l->stream>>>(l->W, dF, B, dO);
@@ -1110,7 +1251,8 @@ extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, floa
     for (uint64_t s = 0; s < k; ++s) {
         BoxView v = b->view(b->cur);
         const BoxView pv = in_place(v);
-        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + 63) / 64, 64, lds, b->stream>>>(pv, p, lv);
+        constexpr uint32_t nt = 64 * kLearnWaves;
+        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + nt - 1) / nt, nt, lds, b->stream>>>(pv, p, lv);
         v.offset = 1;  // binned for the next sweep
         launch_rebin(v, b->stream);
         launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
