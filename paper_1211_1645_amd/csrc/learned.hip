@@ -45,13 +45,19 @@ struct PackedW {
     uint16_t w3t[64 * 32];
     float b1[64], b2[64], b3[32];
 };
-// The part the inference kernels load into LDS.
-struct PackedWInfer {
-    uint16_t w1[64 * 32];
-    uint16_t w2[64 * 64];
-    uint16_t w3[32 * 64];
+// The inference weights in LDS, as the MFMA A-operand fragments of the
+// transposed products: fragment f = nt * KS + ks holds, for lane l, the four
+// bf16 W[16 nt + l%16][16 ks + 4 (l/16) ..+3], so that a wave reads a
+// fragment as 512 consecutive bytes (no bank conflicts).
+struct InferW {
+    v4s w1[8][64];   // 4 row tiles x 2 k-steps
+    v4s w2[16][64];  // 4 x 4
+    v4s w3[8][64];   // 2 x 4 (outputs 0..31)
     float b1[64], b2[64], b3[32];
 };
+// Row strides in LDS of the network input (bf16) and output (fp32), padded
+// so that the 16 rows a wave touches at once fall in different banks.
+constexpr int kXS = 40, kOS = 33;
 
 __host__ __device__ inline uint16_t f2bf(float f) {
     uint32_t u;
@@ -186,8 +192,8 @@ __device__ inline void mlp_forward_wave(const WT &W, const FwdBufs &B) {
 // accumulator rows 4(l/16)..+3 of column l%16, which is exactly how the next
 // layer's B operand is laid out, so between layers the activations only pass
 // through the bias, SiLU and the rounding to bf16 in place.  Only the input
-// rows X (bf16 [64][32]) and the outputs OUT (fp32 [64][32], the 20 used in
-// columns 0..19) go through LDS; OUT must not overlap X.
+// rows X (bf16 [64][kXS], 32 used) and the outputs OUT (fp32 [64][kOS], the
+// 20 used in columns 0..19) go through LDS; OUT must not overlap X.
 __device__ inline float silu_fast(float v) {
     return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
 }
@@ -199,8 +205,7 @@ __device__ inline v4s act_bf16(v4f c, const float *bias, int n0) {
     return r;
 }
 
-template <class WT>
-__device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT) {
+__device__ inline void mlp_infer_wave(const InferW &W, const uint16_t *X, float *OUT) {
     const int l = threadIdx.x & 63, r = l & 15, kg = (l >> 4) * 4;
 #pragma unroll 1
     for (int mt = 0; mt < 4; ++mt) {
@@ -209,10 +214,10 @@ __device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT
         for (int nt = 0; nt < 4; ++nt) c1[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            const v4s b = *reinterpret_cast<const v4s *>(X + (16 * mt + r) * 32 + 16 * ks + kg);
+            const v4s b = *reinterpret_cast<const v4s *>(X + (16 * mt + r) * kXS + 16 * ks + kg);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                const v4s a = *reinterpret_cast<const v4s *>(W.w1 + (16 * nt + r) * 32 + 16 * ks + kg);
+                const v4s a = W.w1[nt * 2 + ks][l];
                 c1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c1[nt], 0, 0, 0);
             }
         }
@@ -226,7 +231,7 @@ __device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                const v4s a = *reinterpret_cast<const v4s *>(W.w2 + (16 * nt + r) * 64 + 16 * ks + kg);
+                const v4s a = W.w2[nt * 4 + ks][l];
                 c2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[ks], c2[nt], 0, 0, 0);
             }
         v4s h2[4];
@@ -239,7 +244,7 @@ __device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
-                const v4s a = *reinterpret_cast<const v4s *>(W.w3 + (16 * nt + r) * 64 + 16 * ks + kg);
+                const v4s a = W.w3[nt * 4 + ks][l];
                 c3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h2[ks], c3[nt], 0, 0, 0);
             }
 #pragma unroll
@@ -247,7 +252,7 @@ __device__ inline void mlp_infer_wave(const WT &W, const uint16_t *X, float *OUT
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int n = 16 * nt + kg + e;
-                OUT[(16 * mt + r) * 32 + n] = c3[nt][e] + W.b3[n];
+                OUT[(16 * mt + r) * kOS + n] = c3[nt][e] + W.b3[n];
             }
     }
     wave_sync();
@@ -440,21 +445,33 @@ struct LearnView {
 
 constexpr int kLearnWaves = 4;  // waves per workgroup of the learned pass
 
+constexpr int kSS = 37;  // per-lane feature scratch stride (floats), odd: no bank conflicts
+
 struct LdsLearn {
-    PackedWInfer w;  // shared by the workgroup's waves
+    InferW w;  // shared by the workgroup's waves
     struct Wave {
-        uint16_t X[64 * 32];  // network input rows
-        float so[64 * 36];    // feature scratch, then the network output [64][32]
+        uint16_t X[64 * kXS];  // network input rows
+        float so[64 * kSS];    // feature scratch, then the network output [64][kOS]
     } pw[kLearnWaves];
 };
 
-// Copies the inference weights into LDS with all threads of the workgroup.
-__device__ inline void load_infer_weights(PackedWInfer &dstw, const PackedW *W, int tid,
-                                          int nthreads) {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(W);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&dstw);
-    constexpr uint32_t nw = (64 * 32 + 64 * 64 + 32 * 64) / 2;  // w1, w2, w3 words
-    for (uint32_t k = tid; k < nw; k += nthreads) dst[k] = src[k];
+// Copies the inference weights into LDS in fragment order, with all threads
+// of the workgroup.
+__device__ inline void load_infer_weights(InferW &dstw, const PackedW *W, int tid, int nthreads) {
+    for (int i = tid; i < 32 * 64; i += nthreads) {
+        const int f = i >> 6, l = i & 63;
+        const uint16_t *src;
+        v4s *dst;
+        int K, nt, ks;
+        if (f < 8) {
+            nt = f >> 1, ks = f & 1, K = 32, src = W->w1, dst = &dstw.w1[f][l];
+        } else if (f < 24) {
+            nt = (f - 8) >> 2, ks = (f - 8) & 3, K = 64, src = W->w2, dst = &dstw.w2[f - 8][l];
+        } else {
+            nt = (f - 24) >> 2, ks = (f - 24) & 3, K = 64, src = W->w3, dst = &dstw.w3[f - 24][l];
+        }
+        *dst = *reinterpret_cast<const v4s *>(src + (16 * nt + (l & 15)) * K + 16 * ks + 4 * (l >> 4));
+    }
     for (int k = tid; k < 64; k += nthreads) {
         dstw.b1[k] = W->b1[k];
         dstw.b2[k] = W->b2[k];
@@ -482,7 +499,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     const uint32_t n = valid ? v.cnt_out[cell] : 0;
     const int Dm = (int)v.step_m << 14;  // d in q units
     const float log_u = -2.0f * logf((float)(2 * Dm + 1) * kQ);
-    float *scr = P.so + 36 * lane;  // scratch before the MLP
+    float *scr = P.so + kSS * lane;  // scratch before the MLP
     uint32_t trials = 0, accepts = 0;
     uint32_t perm = 0x76543210u;
     if (n > 1 && v.n_trial > 1) {
@@ -520,16 +537,16 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         // sorted features into this lane's row of X
         if (act) {
             const int nf = lane_features(nbh, v.x_out, v.y_out, v.w, slot, x, y, scr,
-                                         P.X + 32 * lane, nullptr);
+                                         P.X + kXS * lane, nullptr);
             if (nf > 12) atomicAdd(lv.nfeat_over, 1ull);
         } else {
-            zero_row(P.X + 32 * lane);
+            zero_row(P.X + kXS * lane);
         }
         wave_sync();
         float *OUT = P.so;
         mlp_infer_wave(L.w, P.X, OUT);
         // propose
-        Gmm g = gmm_from(OUT + 32 * lane);
+        Gmm g = gmm_from(OUT + kOS * lane);
         const uint32_t eps_u = (uint32_t)fminf(lv.eps * 4294967296.0f, 4294967295.0f);
         int Dx, Dy;
         bool drawn = true;  // a Gaussian draw beyond +-1 sigma per axis is rejected
@@ -570,15 +587,15 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         // reverse density at x' (every lane takes part in the wave GEMMs)
         wave_sync();
         if (ok) {
-            lane_features(nbh, v.x_out, v.y_out, v.w, slot, xn, yn, scr, P.X + 32 * lane, nullptr);
+            lane_features(nbh, v.x_out, v.y_out, v.w, slot, xn, yn, scr, P.X + kXS * lane, nullptr);
         } else {
-            zero_row(P.X + 32 * lane);
+            zero_row(P.X + kXS * lane);
         }
         wave_sync();
         mlp_infer_wave(L.w, P.X, OUT);
         if (act) ++trials;
         if (ok) {
-            const Gmm gr = gmm_from(OUT + 32 * lane);
+            const Gmm gr = gmm_from(OUT + kOS * lane);
             const float lq_r = log_q(gr, -dxf, -dyf, -Dx, -Dy, Dm, lv.eps, log_u);
             const float ua = ((float)(w2.w3 >> 8) + 0.5f) * (1.0f / 16777216.0f);
             if (logf(ua) < lq_r - lq_f) {
@@ -873,9 +890,9 @@ __global__ void __launch_bounds__(64) k_train(TrainView tv) {
 // Forward only, for given features (diagnostic): out[B][20].
 // It runs the sampler's inference path (mlp_infer_wave).
 struct LdsForward {
-    PackedWInfer w;
-    uint16_t X[64 * 32];
-    float OUT[64 * 32];
+    InferW w;
+    uint16_t X[64 * kXS];
+    float OUT[64 * kOS];
 };
 
 __global__ void __launch_bounds__(64) k_forward(const PackedW *W, const float *F, uint32_t B,
@@ -885,11 +902,11 @@ __global__ void __launch_bounds__(64) k_forward(const PackedW *W, const float *F
     const int lane = threadIdx.x;
     load_infer_weights(L.w, W, lane, 64);
     const uint32_t s = blockIdx.x * 64 + lane;
-    for (int k = 0; k < 32; ++k) L.X[32 * lane + k] = (s < B && k < 24) ? f2bf(F[(size_t)s * 24 + k]) : 0;
+    for (int k = 0; k < 32; ++k) L.X[kXS * lane + k] = (s < B && k < 24) ? f2bf(F[(size_t)s * 24 + k]) : 0;
     __syncthreads();
     mlp_infer_wave(L.w, L.X, L.OUT);
     if (s < B)
-        for (int k = 0; k < 20; ++k) out[(size_t)s * 20 + k] = L.OUT[32 * lane + k];
+        for (int k = 0; k < 20; ++k) out[(size_t)s * 20 + k] = L.OUT[kOS * lane + k];
 }
 
 // Adam on the fp32 master vector; rewrites the packed bf16 weights and
