@@ -117,6 +117,9 @@ def copy_calibration(nbytes=512 << 20, reps=3):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}))
 
 
+LEARN_STEP_FACTOR = 3
+
+
 def learned_comparison(seed, minutes_budget=0.5):
     """Learned proposal against the uniform one on the same w >= 3 cell grid
     at N = 1024^2, eta = 0.716: train on accepted moves of an N = 256^2 box,
@@ -129,6 +132,10 @@ def learned_comparison(seed, minutes_budget=0.5):
     tb = mp.Box(65536, ETA, seed=seed + 1, step_m=40, cell_min=3.0, schedule="simple")
     m_train, _ = tune_step(tb)
     tb.sweep(200)
+    # the moves learned from are the plain sampler's accepted moves at three
+    # times its tuned step: the network then proposes the larger moves that
+    # the neighbourhood allows
+    tb.set_step(min(255, LEARN_STEP_FACTOR * m_train))
     L = mp.Learner(seed=seed + 2, capacity=1 << 22)
     n = L.collect(tb, 150)
     t0 = time.perf_counter()
@@ -137,7 +144,8 @@ def learned_comparison(seed, minutes_budget=0.5):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     progress("learned proposal trained on %d moves in %.1f s" % (n, train_s))
-    out = {"train": {"moves": n, "steps": 3001, "batch": 8192, "loss_first": loss0,
+    out = {"train": {"moves": n, "step_m": min(255, LEARN_STEP_FACTOR * m_train),
+                     "tuned_step_m": m_train, "steps": 3001, "batch": 8192, "loss_first": loss0,
                      "loss_last": loss, "seconds": train_s}}
     for mode in ("uniform", "learned"):
         b = mp.Box(N_DISKS, ETA, seed=seed + 3, step_m=40, cell_min=3.0, schedule="simple")

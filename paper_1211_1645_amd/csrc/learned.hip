@@ -198,11 +198,15 @@ __device__ inline float silu_fast(float v) {
     return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
 }
 
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+// Bias, SiLU and rounding to bf16 (to nearest even, the hardware's packed
+// conversion) of four accumulator rows.
 __device__ inline v4s act_bf16(v4f c, const float *bias, int n0) {
-    v4s r;
+    v4bf h;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = (short)f2bf(silu_fast(c[e] + bias[n0 + e]));
-    return r;
+    for (int e = 0; e < 4; ++e) h[e] = (__bf16)silu_fast(c[e] + bias[n0 + e]);
+    return __builtin_bit_cast(v4s, h);
 }
 
 __device__ inline void mlp_infer_wave(const InferW &W, const uint16_t *X, float *OUT) {
@@ -485,8 +489,9 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     LdsLearn &L = *reinterpret_cast<LdsLearn *>(lds_raw);
     const int lane = threadIdx.x & 63;
     LdsLearn::Wave &P = L.pw[threadIdx.x >> 6];
+    // the weights' copy overlaps the first trial's loads and random numbers:
+    // the barrier that completes it comes just before the first network
     load_infer_weights(L.w, lv.W, threadIdx.x, 64 * kLearnWaves);
-    __syncthreads();
     const uint32_t M = v.M, h = M / 2;
     const uint32_t t = blockIdx.x * (64 * kLearnWaves) + threadIdx.x;
     const uint64_t sweep = v.dev->sweep + v.offset;
@@ -496,7 +501,13 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     const uint32_t ci = valid ? 2 * (t % h) + (colour & 1u) : 0;
     const uint32_t cj = valid ? 2 * (t / h) + (colour >> 1) : 0;
     const uint32_t cell = ci + M * cj;
-    const uint32_t n = valid ? v.cnt_out[cell] : 0;
+    // the neighbourhood (own cell k = 4 included) in one round trip; it is
+    // frozen during a trial and serves the forward features, the overlap
+    // test and the reverse features, and it is read again for every further
+    // trial of the cell
+    Nbhd nbh;
+    if (valid) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
+    const uint32_t n = valid ? (nbh.m >> 12) & 7u : 0u;
     const int Dm = (int)v.step_m << 14;  // d in q units
     const float log_u = -2.0f * logf((float)(2 * Dm + 1) * kQ);
     float *scr = P.so + kSS * lane;  // scratch before the MLP
@@ -522,17 +533,14 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         Words w4{0, 0, 0, 0}, w2{0, 0, 0, 0};
         uint32_t slot = 0;
         float x = 0.0f, y = 0.0f;
+        if (act && tr > 0) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
         if (act) {
             w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
             w2 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
             slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
-            x = v.x_out[slot_at(cell, slot, M * M)];
-            y = v.y_out[slot_at(cell, slot, M * M)];
+            x = slot == 0 ? nbh.x[4][0] : slot == 1 ? nbh.x[4][1] : v.x_out[slot_at(cell, slot, M * M)];
+            y = slot == 0 ? nbh.y[4][0] : slot == 1 ? nbh.y[4][1] : v.y_out[slot_at(cell, slot, M * M)];
         }
-        // the neighbourhood is frozen during the trial: loaded once for the
-        // forward features, the overlap test and the reverse features
-        Nbhd nbh;
-        if (act) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
         wave_sync();
         // sorted features into this lane's row of X
         if (act) {
@@ -543,6 +551,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
             zero_row(P.X + kXS * lane);
         }
         wave_sync();
+        if (tr == 0) __syncthreads();  // the weights are in LDS
         float *OUT = P.so;
         mlp_infer_wave(L.w, P.X, OUT);
         // propose
