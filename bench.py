@@ -291,6 +291,65 @@ TAU_N, TAU_ETA = 512 * 512, 0.698
 TAU_PAPER_DISP = 8.0e5   # MPMC correlation time of Psi_6 in displacements per disk (Table II)
 
 
+SCALE_N = 4096 * 4096
+
+
+def scale_bench(args):
+    """The plain sweep on the scale probe N = 4096^2 (16.8 M disks, state
+    of about 440 MB per sweep, beyond the 256 MB Infinity Cache): sweeps/s,
+    trial moves/s and the roofline fractions of the same kernel."""
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        box = mp.Box(SCALE_N, ETA, seed=args.seed, step_m=55, lattice="triangular",
+                     stream=stream.cuda_stream)
+        box.set_graphs(args.sweeps)
+        step_m, _ = tune_step(box, block=20)
+        info = box.info()
+        progress("scale probe: M=%d schedule %d tile %d m=%d" %
+                 (info["M"], info["schedule"], info["tile"], step_m))
+        for _ in range(args.warmup):
+            box.sweep(args.sweeps)
+        torch.cuda.synchronize()
+        t_before = box.info()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            box.sweep(args.sweeps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_after = box.info()
+        overlaps, bad = box.validate()
+    k = args.steps * args.sweeps
+    sweep_s = e0.elapsed_time(e1) * 1e-3 / k
+    trials = t_after["trials"] - t_before["trials"]
+    bytes_per = algorithmic_bytes_per_sweep(info["N"], info["M"])
+    ops_per = trials / k * alu_ops_per_trial(info["N"], info["M"])
+    line = {
+        "metric": "trial moves/s, 4096^2 disks eta=0.716 (scale probe)",
+        "value": trials / (sweep_s * k), "unit": "trial moves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sweep_s * args.sweeps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (triangular-lattice start, Philox4x32-10 seed %d)" % args.seed,
+        "config": {"workload": "plain MPMC scale probe, N=4096^2, eta=0.716, step tuned to "
+                               "~30%% acceptance (m=%d), %d sweeps per step" % (step_m, args.sweeps),
+                   "N": info["N"], "M": info["M"], "tile": info["tile"],
+                   "schedule": "fused" if info["schedule"] == 2 else "simple"},
+        "sweep_us": sweep_s * 1e6,
+        "acceptance": (t_after["accepts"] - t_before["accepts"]) / max(trials, 1),
+        "validate": {"overlaps": overlaps, "bad": bad},
+        "roofline": {"bound": "alu", "achieved": ops_per / sweep_s / 1e12, "peak": ALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": ops_per / sweep_s / 1e12 / ALU_PEAK_TOPS,
+                     "traffic": None, "kernel": "k_fused (one sweep per launch)",
+                     "hbm": {"achieved": bytes_per / sweep_s / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": bytes_per / sweep_s / 1e9 / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": bytes_per}},
+    }
+    print(json.dumps(line))
+
+
 def tau_analysis(series, sample, disp_per_sweep, discard):
     """tau of a Psi_6 series sampled every `sample` sweeps: the exponential
     fit of Sec. III over 0.05 <= C <= 0.5, the e-folding lag (first C < 1/e,
@@ -423,9 +482,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "positional", "tau"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "positional", "tau", "scale"),
+                    default="sweep",
                     help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
-                         "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes)")
+                         "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes); "
+                         "scale: the sweep at N=4096^2")
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
     ap.add_argument("--tau-discard", type=int, default=4000000)
     ap.add_argument("--tau-sample", type=int, default=1000)
@@ -450,6 +511,9 @@ def main():
         return
     if args.workload == "tau":
         tau_bench(args)
+        return
+    if args.workload == "scale":
+        scale_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
