@@ -291,6 +291,67 @@ TAU_N, TAU_ETA = 512 * 512, 0.698
 TAU_PAPER_DISP = 8.0e5   # MPMC correlation time of Psi_6 in displacements per disk (Table II)
 
 
+def batch_bench(args):
+    """Many independent boxes of uneven size and density swept together: 64
+    boxes with N drawn from {64^2, 96^2, 128^2, 192^2, 256^2} and eta uniform
+    in [0.69, 0.73] (seeded), one persistent graph-captured launch per sweep,
+    against the same boxes each swept by its own launches (fused kernel,
+    autotuned shape, graphs)."""
+    import numpy as np
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    from paper_1211_1645_amd.workloads import batch_boxes
+    N, eta, seeds = batch_boxes(64, seed=args.seed)
+    b = mp.Batch(N, eta, seeds, step_m=40)
+    b.set_graphs(args.sweeps)
+    b.sweep(args.sweeps)
+    torch.cuda.synchronize()
+    inf = b.info()
+    k = args.steps * args.sweeps
+    t0 = time.perf_counter()
+    tr, ac = b.sweep(k, counts=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for _ in range(2):
+        b.accumulate_contacts()
+        b.sweep(10)
+    progress("batch: %d sweeps of %d boxes in %.3f s" % (k, len(N), dt))
+    # the same boxes one at a time
+    boxes = [mp.Box(int(n), float(e), seed=int(sd), step_m=40) for n, e, sd in zip(N, eta, seeds)]
+    for bx in boxes:
+        bx.set_graphs(args.sweeps)
+        bx.sweep(args.sweeps)
+    torch.cuda.synchronize()
+    ks = max(args.sweeps, k // 4)
+    t0 = time.perf_counter()
+    tr1 = 0
+    for bx in boxes:
+        i0 = bx.info()["trials"]
+        bx.sweep(ks)
+        torch.cuda.synchronize()
+        tr1 += bx.info()["trials"] - i0
+    dt1 = time.perf_counter() - t0
+    line = {
+        "metric": "trial moves/s, 64-box batch (N from 64^2 to 256^2, eta 0.69-0.73)",
+        "value": tr / dt, "unit": "trial moves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (triangular-lattice starts, Philox4x32-10 seeds %d..%d)" %
+                (args.seed, args.seed + 63),
+        "config": {"workload": "64 independent boxes, one persistent launch per sweep, %d "
+                               "sweeps per step" % args.sweeps,
+                   "N_total": int(N.sum()), "tile": inf["tile"], "threads": inf["threads"]},
+        "batch_sweep_us": dt / k * 1e6,
+        "acceptance": ac / max(tr, 1),
+        "one_box_at_a_time": {"trial_moves_per_s": tr1 / dt1,
+                              "sweep_of_all_boxes_us": dt1 / ks * 1e6},
+        "speedup_over_one_at_a_time": (tr / dt) / (tr1 / dt1),
+        "P_star_first_boxes": [float(x) for x in b.measure_pressure()[0][:4]],
+    }
+    print(json.dumps(line))
+
+
 SCALE_N = 4096 * 4096
 
 
@@ -482,11 +543,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "positional", "tau", "scale"),
+    ap.add_argument("--workload", choices=("sweep", "positional", "tau", "scale", "batch"),
                     default="sweep",
                     help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
                          "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes); "
-                         "scale: the sweep at N=4096^2")
+                         "scale: the sweep at N=4096^2; batch: 64 boxes in one launch")
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
     ap.add_argument("--tau-discard", type=int, default=4000000)
     ap.add_argument("--tau-sample", type=int, default=1000)
@@ -514,6 +575,9 @@ def main():
         return
     if args.workload == "scale":
         scale_bench(args)
+        return
+    if args.workload == "batch":
+        batch_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):

@@ -178,8 +178,8 @@ int mpmc_structure_factor(mpmc_box b, const int32_t *hk, uint32_t nq, double *S)
  * q_lo <= |q| <= q_hi and direction atan2(k, h) in [theta0, theta0 + dtheta)
  * modulo 2 pi (radians; dtheta >= 2 pi means every direction), the one with
  * the largest S (the first in the order k, then h ascending on ties).
- * Outputs may be NULL.  MPMC_EINVAL if the window is empty or q_hi reaches
- * the index limit. */
+ * Outputs may be NULL.  MPMC_EINVAL if the window is empty, q_hi reaches
+ * the index limit or the annulus holds more than 2^24 wave vectors. */
 int mpmc_find_q0(mpmc_box b, double q_lo, double q_hi, double theta0, double dtheta,
                  int32_t *h, int32_t *k, double *S);
 

@@ -22,6 +22,7 @@ Box *B(mpmc_box b) { return reinterpret_cast<Box *>(b); }
 constexpr int32_t kMaxIndex = 4096;   // |h|, |k| below this
 constexpr uint32_t kChunk = 65536;    // wave vectors per launch
 constexpr uint32_t kMaxBins = 4096;   // C_q windows (LDS: 12 bytes each)
+constexpr uint32_t kMaxScan = 1u << 24;  // wave vectors one q0 search may visit
 constexpr double kQunit = 1.0 / 4194304.0;  // 2^-22
 
 // S at nq wave vectors (host hk, host S), in launches of at most kChunk.
@@ -86,6 +87,11 @@ extern "C" int mpmc_find_q0(mpmc_box bh, double q_lo, double q_hi, double theta0
     const double full = 2.0 * M_PI;
     std::vector<int32_t> hk;
     const int32_t r = (int32_t)ceil(n_hi);
+    // every index pair of the annulus owns a unit square inside the annulus
+    // widened by sqrt 2 on both sides, so this area bounds their number
+    const double wlo = fmax(0.0, sqrt(n2lo) - M_SQRT2), whi = n_hi + M_SQRT2;
+    if (M_PI * (whi * whi - wlo * wlo) > (double)kMaxScan)
+        return fail(MPMC_EINVAL, "search window holds more than %u wave vectors", kMaxScan);
     for (int32_t k = -r; k <= r; ++k)
         for (int32_t h = -r; h <= r; ++h) {
             const double n2 = (double)h * h + (double)k * k;
