@@ -1,0 +1,45 @@
+"""Host-side pieces of bench.py that need no GPU: the correlation-time
+analysis of a Psi_6 series and the stored-profile readers."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_tau_analysis_on_ar1_series():
+    """A complex AR(1) series Psi(t+1) = phi Psi(t) + noise has C(dt) = phi^dt:
+    tau = -1/ln(phi) samples and the e-folding lag is its ceiling."""
+    rng = np.random.default_rng(3)
+    phi, n = 0.98, 100000
+    noise = rng.normal(size=n) + 1j * rng.normal(size=n)
+    x = np.empty(n, np.complex128)
+    x[0] = noise[0]
+    for t in range(1, n):
+        x[t] = phi * x[t - 1] + noise[t]
+    sample, disp = 10, 0.5   # sweeps per sample, displacements per disk per sweep
+    res = bench.tau_analysis(x, sample, disp, discard=1000 * sample)
+    tau_s = -1.0 / math.log(phi)   # in samples
+    unit = sample * disp
+    # the e-folding lag and the integrated time are tight at 2000 tau; the
+    # exponential fit over 0.05 <= C <= 0.5 leans on the noisy tail
+    assert res["tau_efold_displacements_per_disk"] == pytest.approx(tau_s * unit, rel=0.08)
+    assert res["tau_int_displacements_per_disk"] == pytest.approx(tau_s * unit, rel=0.1)
+    assert res["tau_displacements_per_disk"] == pytest.approx(tau_s * unit, rel=0.3)
+    assert res["tau_sweeps"] == pytest.approx(res["tau_displacements_per_disk"] / disp)
+    for h in res["tau_efold_halves_displacements_per_disk"]:
+        assert h == pytest.approx(tau_s * unit, rel=0.12)
+
+
+def test_stored_profiles_are_readable():
+    tau = bench.stored_tau()
+    assert tau is not None and tau["paper_tau_displacements_per_disk"] == 8.0e5
+    assert tau["tau_efold_displacements_per_disk"] > 0
+    # the traffic figure is reported only for the kernel source it was taken on
+    t = bench.stored_traffic()
+    assert t is None or t > bench.algorithmic_bytes_per_sweep(1024 * 1024, 1072)
