@@ -195,11 +195,18 @@ __global__ void __launch_bounds__(256) k_cq(MeasureView m, double qx, double qy,
     const long long one = 1ll << 22;
     const uint32_t n = c < NC ? m.cnt[c] : 0u;
     const int ci = (int)(c % M), cj = (int)(c / M);
+    const double inv_dr = 1.0 / dr;  // candidate windows only: each is confirmed exactly
+    // a neighbour cell whose nearest corner lies beyond the reach holds no
+    // partner: (|di| - 1)^2 + (|dj| - 1)^2 > (reach / W)^2 in cells
+    const double rc = (double)reach / (double)m.W, rc2 = rc * rc;
     for (uint32_t s = 0; s < n; ++s) {
         const long long Ui = (long long)(m.x[slot_at(c, s, NC)] * 4194304.0f);
         const long long Vi = (long long)(m.y[slot_at(c, s, NC)] * 4194304.0f);
-        for (int dj = -R; dj <= R; ++dj)
+        for (int dj = -R; dj <= R; ++dj) {
+            const double ey = (double)(abs(dj) > 0 ? abs(dj) - 1 : 0);
             for (int di = -R; di <= R; ++di) {
+                const double ex = (double)(abs(di) > 0 ? abs(di) - 1 : 0);
+                if (ex * ex + ey * ey > rc2) continue;
                 const uint32_t nb = wrapm(ci + di, M) + M * wrapm(cj + dj, M);
                 const uint32_t mm = m.cnt[nb];
                 for (uint32_t t = 0; t < mm; ++t) {
@@ -212,8 +219,8 @@ __global__ void __launch_bounds__(256) k_cq(MeasureView m, double qx, double qy,
                     const unsigned long long d2 = (unsigned long long)(dX * dX) +
                                                   (unsigned long long)(dY * dY);
                     const double d = sqrt((double)d2) * (1.0 / 4194304.0);
-                    long long b0 = (long long)floor((d - 1.0) / dr) - 1;
-                    long long b1 = (long long)ceil((d + 1.0) / dr) + 1;
+                    long long b0 = (long long)floor((d - 1.0) * inv_dr) - 1;
+                    long long b1 = (long long)ceil((d + 1.0) * inv_dr) + 1;
                     if (b0 < 0) b0 = 0;
                     if (b1 > (long long)B - 1) b1 = (long long)B - 1;
                     if (b0 > b1) continue;
@@ -229,6 +236,7 @@ __global__ void __launch_bounds__(256) k_cq(MeasureView m, double qx, double qy,
                     }
                 }
             }
+        }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < B; b += blockDim.x) {
