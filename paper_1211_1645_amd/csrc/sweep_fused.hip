@@ -62,16 +62,11 @@ struct Lds {
     static constexpr int R = RL + 1;                 // allocated side (even)
     static constexpr int NC = R * R;
     static constexpr int TE = TILE + 1;              // extended block side
-    static constexpr int HH = (R / 2) * (R / 2);     // cells of one colour plane
     float4 x[NC];
     float4 y[NC];
     uint8_t cnt[NC];
-    union {
-        uint16_t list[4][HH];   // passes: the non-empty cells each pass updates
-        uint16_t gcnt[TE * TE]; // re-bin: per old cell, disks per wrap class, 3 bits each
-    };
-    uint32_t wsum[4][16];  // per-pass, per-wave counts for the compaction scan
-    uint32_t big;          // some region cell holds more than two disks
+    uint16_t gcnt[TE * TE];  // re-bin: per old cell, disks per wrap class, 3 bits each
+    uint32_t big;            // some region cell holds more than two disks
 };
 
 // LDS index of region cell (rx, ry): colour plane, then row-major in plane.
@@ -179,62 +174,28 @@ __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_
     return bad;
 }
 
-// Lists, for all four passes at once, the non-empty cells each pass updates
-// (colour col[p], region coordinates in [p+1, RL-p-1)); total[p] is the
-// length of list p, the same in every thread.
-template <int TILE, int THREADS>
-__device__ __forceinline__ void compact_passes(Lds<TILE> &L, int tid, const uint32_t col[4],
-                                               int total[4]) {
-    constexpr int RL = Lds<TILE>::RL, H = Lds<TILE>::R / 2, HH = H * H;
-    const uint32_t lane = (uint32_t)tid & 63u, wave = (uint32_t)tid >> 6;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) total[p] = 0;
-    for (int base = 0; base < HH; base += THREADS) {
-        const int a = base + tid;
-        const bool cand = a < HH;
-        const int ax = a % H, ay = a / H;
-        unsigned long long bal[4];
-        bool live[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int rx = 2 * ax + (int)(col[p] & 1u), ry = 2 * ay + (int)(col[p] >> 1);
-            const int lo = p + 1, hi = RL - p - 1;
-            live[p] = cand && rx >= lo && rx < hi && ry >= lo && ry < hi &&
-                      L.cnt[(int)col[p] * HH + (cand ? a : 0)] != 0;
-            bal[p] = __ballot(live[p]);
-            if (lane == 0) L.wsum[p][wave] = (uint32_t)__popcll(bal[p]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            uint32_t before = 0, all = 0;
-#pragma unroll
-            for (uint32_t q = 0; q < THREADS / 64; ++q) {
-                const uint32_t cq = L.wsum[p][q];
-                before += q < wave ? cq : 0u;
-                all += cq;
-            }
-            const uint32_t rank = (uint32_t)__popcll(bal[p] & ((1ull << lane) - 1ull));
-            if (live[p]) L.list[p][total[p] + (int)(before + rank)] = (uint16_t)a;
-            total[p] += (int)all;
-        }
-        __syncthreads();
-    }
-}
-
 // One colour sub-sweep over the LDS region: pass p updates the cells of
-// list p (colour (CX, CY)), one lane per cell.
+// colour (CX, CY) with region coordinates in [p + 1, RL - p - 1), one lane per
+// cell of that rectangle of the colour plane; lanes of empty cells idle.
+// (Listing the non-empty cells first saves those lanes but costs a ballot,
+// a scan and two barriers per pass, more than it saves.)
 template <int TILE, int THREADS, int CX, int CY, typename View>
 __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const PassCtx &ctx,
-                                         int tid, int p, int total, uint32_t &trials,
-                                         uint32_t &accepts) {
+                                         int tid, int p, uint32_t &trials, uint32_t &accepts) {
     constexpr int H = Lds<TILE>::R / 2, PB = (CX | (CY << 1)) * H * H;
+    constexpr int RL = Lds<TILE>::RL;
     const uint32_t M = v.M;
     const float w = v.w, cen = ctx.cen;
     const float lo_b = -cen, hi_b = w - cen;  // in-cell range of centred offsets
-    for (int j = tid; j < total; j += THREADS) {
-        const int a = L.list[p][j];
-        const int ax = a % H, ay = a / H;
+    // plane cells (ax, ay) with 2 ax + CX and 2 ay + CY in [p + 1, RL - p - 1)
+    const int lo = p + 1, hi = RL - p - 1;
+    const int ax0 = (lo - CX + 1) >> 1, ax1 = (hi - CX + 1) >> 1;
+    const int ay0 = (lo - CY + 1) >> 1, ay1 = (hi - CY + 1) >> 1;
+    const int wdt = ax1 - ax0, ncell = wdt * (ay1 - ay0);
+    for (int j = tid; j < ncell; j += THREADS) {
+        const int ax = ax0 + j % wdt, ay = ay0 + j / wdt;
+        const int a = ax + H * ay;
+        if (L.cnt[PB + a] == 0) continue;
         const int rx = 2 * ax + CX, ry = 2 * ay + CY;
         const int e = PB + a;
         const uint32_t n = L.cnt[e];
@@ -377,17 +338,15 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     uint32_t col[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) col[p] = colour_of_pass(d.perm, p);
-    int total[4];
-    compact_passes<TILE, THREADS>(L, tid, col, total);
     uint32_t trials = 0, accepts = 0;
     for (int p = 0; p < 4; ++p) {
         // each colour has its own instantiation with compile-time neighbour
         // offsets
         switch (col[p]) {
-        case 0: run_pass<TILE, THREADS, 0, 0>(L, v, ctx, tid, p, total[p], trials, accepts); break;
-        case 1: run_pass<TILE, THREADS, 1, 0>(L, v, ctx, tid, p, total[p], trials, accepts); break;
-        case 2: run_pass<TILE, THREADS, 0, 1>(L, v, ctx, tid, p, total[p], trials, accepts); break;
-        default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, tid, p, total[p], trials, accepts); break;
+        case 0: run_pass<TILE, THREADS, 0, 0>(L, v, ctx, tid, p, trials, accepts); break;
+        case 1: run_pass<TILE, THREADS, 1, 0>(L, v, ctx, tid, p, trials, accepts); break;
+        case 2: run_pass<TILE, THREADS, 0, 1>(L, v, ctx, tid, p, trials, accepts); break;
+        default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, tid, p, trials, accepts); break;
         }
         __syncthreads();
     }
