@@ -114,12 +114,16 @@ __device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t
     for (int e = threadIdx.x; e < SR * SR; e += blockDim.x) {
         const int rx = e % SR, ry = e / SR;
         const uint32_t c = wrapc((int)I0 - H + rx, M) + M * wrapc((int)J0 - H + ry, M);
+        // count and slots 0, 1 in one round trip (unused slots hold stale
+        // values and are replaced by the sentinel); slots 2, 3 where needed
         uint32_t n = m.cnt[c];
+        const float xa = m.x[c], xb = m.x[NC + c], ya = m.y[c], yb = m.y[NC + c];
+        const uint32_t ta = m.tag[c], tb = m.tag[NC + c];
         n = n > 4 ? 4 : n;
         float4 x4 = make_float4(kFarM, kFarM, kFarM, kFarM), y4 = x4;
         uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
-        if (n > 0) { x4.x = m.x[c]; y4.x = m.y[c]; t4.x = m.tag[c]; }
-        if (n > 1) { x4.y = m.x[NC + c]; y4.y = m.y[NC + c]; t4.y = m.tag[NC + c]; }
+        if (n > 0) { x4.x = xa; y4.x = ya; t4.x = ta; }
+        if (n > 1) { x4.y = xb; y4.y = yb; t4.y = tb; }
         if (n > 2) { x4.z = m.x[2 * NC + c]; y4.z = m.y[2 * NC + c]; t4.z = m.tag[2 * NC + c]; }
         if (n > 3) { x4.w = m.x[3 * NC + c]; y4.w = m.y[3 * NC + c]; t4.w = m.tag[3 * NC + c]; }
         S.x[e] = x4;
