@@ -556,8 +556,8 @@ def main():
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the sampler runs one box per GPU and this build "
-              "has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the sampler runs one box per GPU and the "
+              "library has no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

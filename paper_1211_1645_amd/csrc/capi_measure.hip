@@ -420,7 +420,7 @@ extern "C" int mpmc_load(mpmc_box *out, const char *path, const mpmc_params *pp)
         fclose(f);
         b->release();
         delete b;
-        return fail(MPMC_EIO, "checkpoint geometry does not match this build");
+        return fail(MPMC_EIO, "checkpoint geometry does not match the box these parameters give");
     }
     const size_t nc = (size_t)H.M * H.M, ns = nc * H.CS;
     const uint32_t K = H.hist_bins;
