@@ -27,11 +27,13 @@ constexpr double kQunit = 1.0 / 4194304.0;  // 2^-22
 
 // S at nq wave vectors (host hk, host S), in launches of at most kChunk.
 int structure_factor(Box *b, const int32_t *hk, uint32_t nq, double *S) {
+    int rc = b->read_scalars();  // the accumulated shift places the disks
+    if (rc) return rc;
     const MeasureView m = b->mview();
     const uint32_t chunk = nq < kChunk ? nq : kChunk;
     const size_t part = (rho_work_bytes(m, chunk) + 255) & ~(size_t)255;
     const size_t stage = (size_t)chunk * 8;
-    int rc = b->pos_work_at_least(part + 2 * stage);
+    rc = b->pos_work_at_least(part + 2 * stage);
     if (rc) return rc;
     char *base = static_cast<char *>(b->pos_work);
     int32_t *dhk = reinterpret_cast<int32_t *>(base + part);
@@ -130,6 +132,8 @@ extern "C" int mpmc_chi_field(mpmc_box bh, int32_t h, int32_t k, float *re, floa
         if (rc) return rc;
     }
     float *dre = b->chi_buf, *dim = dre + b->N, *dfr = dim + b->N, *dfi = dfr + nc;
+    int rc = b->read_scalars();  // the accumulated shift places the disks
+    if (rc) return rc;
     const MeasureView m = b->mview();
     launch_chi(m, h, k, dre, dim, b->stream);
     HIPCHK(hipGetLastError());

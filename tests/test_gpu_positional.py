@@ -191,3 +191,18 @@ def test_cq_aligned_matches_oracle_rotation(medium):
     assert np.array_equal(cnt, ocnt)
     top = (B - 1) * dr + 1
     assert np.all(np.abs(num - onum) <= ocnt * (math.hypot(qx, qy) * top * da + 1e-12))
+
+
+def test_chi_right_after_sweeps(gpu_lib):
+    """chi_j depends on absolute positions, hence on the accumulated shift
+    that the sweeps advance on the device: a call straight after sweeps
+    (nothing else read back in between) must see the current shift."""
+    g = gpu_lib.Box(SMALL["N"], SMALL["eta"], seed=4, step_m=26, lattice="square")
+    o = OracleBox(SMALL["N"], SMALL["eta"], seed=4, lattice=0, step_m=26)
+    for k in (1, 7, 64):
+        g.sweep(k)
+        o.sweep(k)
+        chi, _ = g.chi_field(5, -3)
+        assert np.abs(chi - o.chi(5, -3)).max() < 1e-6
+        S = g.structure_factor([[5, -3]])
+        assert abs(S[0] - o.structure_factor([[5, -3]])[0]) <= s_tol(SMALL["N"], S[0])
