@@ -254,6 +254,26 @@ int mpmc_eos_loop(const double *eta, const double *p_star, const double *se, uin
 int mpmc_power_law(const double *x, const double *y, uint32_t n, double *exponent,
                    double *prefactor);
 
+/* Asynchronous measurement of the current configuration: adds it to the
+ * contact histogram (as mpmc_accumulate_contacts) and evaluates psi_6 (as
+ * mpmc_psi6_field, with the stencil half-width of its first attempt) on a
+ * stream of the box's own, so that the kernels overlap the sweeps that
+ * follow; nothing is copied to the host.  Psi (may be NULL): device pointer
+ * to two doubles that receive the global Psi_6 (re, im) once the kernels
+ * have run; field != 0 also refreshes the psi field (mpmc_psi6_field's
+ * buffers).  The next sweeps wait for the measurement only before their last
+ * sweep overwrites the state it reads; every other call on the box waits for
+ * it on the box's stream.  A neighbour search too short for some disk is
+ * not retried: it sets a flag that mpmc_measure_wait reports.  MPMC_EINVAL
+ * with hist_block > 0 or where the staged kernels do not apply (cells of
+ * more than 4 disks, M < 6); MPMC_ESTATE for a box of a batch. */
+int mpmc_measure_async(mpmc_box b, double *Psi, int field);
+
+/* Waits on the host for the asynchronous measurements of the box; *failed
+ * (may be NULL) receives 1 if any of them since the last wait had a
+ * neighbour search too short (its psi values are then not exact), else 0. */
+int mpmc_measure_wait(mpmc_box b, uint32_t *failed);
+
 /* Absolute positions by tag: (i w + u + S) mod L_eff in sigma (double) or
  * in q units (int64); either pair may be NULL. */
 int mpmc_get_positions(mpmc_box b, double *x, double *y, int64_t *X, int64_t *Y);

@@ -109,6 +109,15 @@ void Box::free_dev(void *ptr) {
 }
 
 void Box::release() {
+    if (meas_stream) {
+        hipStreamSynchronize(meas_stream);
+        hipStreamDestroy(meas_stream);
+        meas_stream = nullptr;
+    }
+    if (ev_swept) hipEventDestroy(ev_swept);
+    if (ev_meas) hipEventDestroy(ev_meas);
+    ev_swept = ev_meas = nullptr;
+    meas_pending = false;
     if (graph_exec) hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;
     if (cap_stream) hipStreamDestroy(cap_stream);
@@ -188,10 +197,17 @@ int Box::read_scalars() {
 // Uploads cell lists built on the host (cnt, slot-major tag, x, y) as the
 // canonical state, resets the device scalars, and bins the lists in the
 // grid of the next sweep.
+int Box::join_meas() {
+    if (meas_pending) HIPCHK(hipStreamWaitEvent(stream, ev_meas, 0));
+    return MPMC_OK;
+}
+
 int Box::upload(const std::vector<uint8_t> &hc, const std::vector<uint32_t> &ht,
                 const std::vector<float> &hx, const std::vector<float> &hy,
                 const DevScalars &s) {
     const size_t nc = (size_t)g.M * g.M, ns = nc * g.CS;
+    int jrc = join_meas();
+    if (jrc) return jrc;
     HIPCHK(hipMemcpyAsync(C.cnt, hc.data(), nc, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(C.tag, ht.data(), ns * 4, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(C.x, hx.data(), ns * 4, hipMemcpyHostToDevice, stream));
@@ -213,6 +229,8 @@ int Box::upload(const std::vector<uint8_t> &hc, const std::vector<uint32_t> &ht,
 
 int Box::materialize() {
     if (canon_in_c) return MPMC_OK;
+    int jrc = join_meas();
+    if (jrc) return jrc;
     const size_t nc = (size_t)g.M * g.M, ns = nc * g.CS;
     const CellBuf s = P[cur ^ 1];
     HIPCHK(hipMemcpyAsync(C.cnt, s.cnt, nc, hipMemcpyDeviceToDevice, stream));
@@ -375,12 +393,14 @@ int Box::build_graph() {
         hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
     }
+    // the graph holds the first G - 1 sweeps of a run; the last one, which
+    // writes the canonical state, and the counter update are launched
+    // directly after it, so that the run can wait for a pending measurement
+    // of the previous canonical state just before overwriting it
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-    for (uint32_t k = 0; k < graph_sweeps; ++k)
-        launch_one((int)(k & 1u), k, cap_stream, k + 1 == graph_sweeps);
-    launch_advance(dev, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)g.W, g.Lq,
-                   graph_sweeps, cap_stream);
+    for (uint32_t k = 0; k + 1 < graph_sweeps; ++k)
+        launch_one((int)(k & 1u), k, cap_stream, false);
     HIPCHK(hipStreamEndCapture(cap_stream, &graph));
     hipError_t e = hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
@@ -406,10 +426,20 @@ int Box::run_sweeps(uint64_t k) {
                 if (rc) return rc;
             }
             HIPCHK(hipGraphLaunch(graph_exec, stream));
+            int jrc = join_meas();
+            if (jrc) return jrc;
+            launch_one((int)((graph_sweeps - 1) & 1u), graph_sweeps - 1, stream, true);
+            launch_advance(dev, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)g.W, g.Lq,
+                           graph_sweeps, stream);
+            HIPCHK(hipGetLastError());
             k -= graph_sweeps;
             host_sweeps += graph_sweeps;
             canon_in_c = sched != MPMC_SCHED_SIMPLE;
             continue;
+        }
+        if (k == 1 || sched == MPMC_SCHED_SIMPLE) {  // writes the canonical state
+            int jrc = join_meas();
+            if (jrc) return jrc;
         }
         launch_one(cur, 0, stream, k == 1);
         launch_advance(dev, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)g.W, g.Lq, 1, stream);

@@ -105,6 +105,7 @@ static int pressure_from_counts(const Box *b, const unsigned long long *ordered,
 extern "C" int mpmc_accumulate_contacts(mpmc_box bh) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     if (b->N < 2) return fail(MPMC_EINVAL, "need at least two disks");
     const uint32_t K = b->p.hist_bins;
     const double rmax = 2.0 + K * b->p.hist_dr;
@@ -136,6 +137,7 @@ extern "C" int mpmc_accumulate_contacts(mpmc_box bh) {
 extern "C" int mpmc_reset_contacts(mpmc_box bh) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     HIPCHK(hipMemsetAsync(b->hist, 0, b->p.hist_bins * 8, b->stream));
     b->n_conf = 0;
     b->block_conf0 = 0;
@@ -147,6 +149,7 @@ extern "C" int mpmc_reset_contacts(mpmc_box bh) {
 extern "C" int mpmc_get_contacts(mpmc_box bh, int64_t *counts, uint64_t *n_conf) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     const uint32_t K = b->p.hist_bins;
     std::vector<unsigned long long> h(K);
     HIPCHK(hipMemcpyAsync(h.data(), b->hist, K * 8, hipMemcpyDeviceToHost, b->stream));
@@ -161,6 +164,7 @@ extern "C" int mpmc_measure_pressure(mpmc_box bh, double *p_star, double *g_cont
                                      double *se) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     if (b->n_conf == 0) return fail(MPMC_ESTATE, "no configuration accumulated");
     const uint32_t K = b->p.hist_bins;
     std::vector<unsigned long long> h(K);
@@ -186,6 +190,7 @@ extern "C" int mpmc_measure_pressure(mpmc_box bh, double *p_star, double *g_cont
 extern "C" int mpmc_contact_hist_subset(mpmc_box bh, const uint8_t *sel, int64_t *counts) {
     if (!bh || !sel || !counts) return fail(MPMC_EINVAL, "NULL argument");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     const uint32_t K = b->p.hist_bins;
     uint8_t *dsel = nullptr;
     unsigned long long *dh = nullptr;
@@ -227,6 +232,7 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
                                double *Psi_re, double *Psi_im, int on_device) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     if (b->N < 7) return fail(MPMC_EINVAL, "psi_6 needs at least 7 disks");
     const uint32_t M = b->g.M;
     const size_t nc = (size_t)M * M;
@@ -270,6 +276,84 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
     }
     if (Psi_re) *Psi_re = b->host.psi_re / (double)b->N;
     if (Psi_im) *Psi_im = b->host.psi_im / (double)b->N;
+    return MPMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The contact histogram and psi_6 of the current configuration on a stream of
+// the box's own, so that they overlap the sweeps that follow: the kernels
+// read the canonical state C, which the next run of sweeps overwrites only in
+// its last sweep, after waiting for them.
+int Box::measure_async(double *Psi_dev, bool field) {
+    if (in_batch) return fail(MPMC_ESTATE, "a batch box is measured through its batch");
+    if (N < 7) return fail(MPMC_EINVAL, "psi_6 needs at least 7 disks");
+    if (p.hist_block > 0) return fail(MPMC_EINVAL, "asynchronous measurement keeps no pressure blocks (hist_block must be 0)");
+    const uint32_t K = p.hist_bins;
+    const double rmax = 2.0 + K * p.hist_dr;
+    const uint32_t hc = ((double)g.w >= rmax) ? 1u : 2u;
+    const uint32_t hmax = (g.M - 2) / 2;
+    const uint32_t hp = hmax < 2 ? hmax : 2;
+    if (hp < 1 || !measure_tiled(mview(), hc) || !measure_tiled(mview(), hp))
+        return fail(MPMC_EINVAL, "asynchronous measurement needs the staged kernels (cells of at most 4 disks, a box of at least 6 cells)");
+    int rc = materialize();  // the kernels read C
+    if (rc) return rc;
+    rc = measure_work();
+    if (rc) return rc;
+    const size_t nc = (size_t)g.M * g.M;
+    if (!psi_buf) {
+        rc = alloc_dev((void **)&psi_buf, (2 * (size_t)N + 2 * nc) * 4);
+        if (rc) return rc;
+    }
+    if (!async_fail) {
+        rc = alloc_dev((void **)&async_fail, 4);
+        if (rc) return rc;
+        HIPCHK(hipMemsetAsync(async_fail, 0, 4, stream));
+    }
+    if (!meas_stream) {
+        HIPCHK(hipStreamCreateWithFlags(&meas_stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev_swept, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_meas, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(ev_swept, stream));
+    HIPCHK(hipStreamWaitEvent(meas_stream, ev_swept, 0));
+    const MeasureView m = mview();
+    launch_contact_hist(m, edges, K, hc, hist, nullptr, loc, meas_work, meas_stream);
+    HIPCHK(hipGetLastError());
+    ++n_conf;
+    float *dre = psi_buf, *dim = dre + N, *dfr = dim + N, *dfi = dfr + nc;
+    launch_psi6(m, hp, dre, dim, async_fail, loc, meas_work, meas_stream);
+    HIPCHK(hipGetLastError());
+    if (field) {
+        launch_psi6_field(m, dre, dim, dfr, dfi, meas_stream);
+        HIPCHK(hipGetLastError());
+    }
+    if (Psi_dev) {
+        launch_psi_mean(dev, N, Psi_dev, meas_stream);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipEventRecord(ev_meas, meas_stream));
+    meas_pending = true;
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_measure_async(mpmc_box bh, double *Psi, int field) {
+    if (!bh) return fail(MPMC_EINVAL, "NULL box");
+    return B(bh)->measure_async(Psi, field != 0);
+}
+
+extern "C" int mpmc_measure_wait(mpmc_box bh, uint32_t *failed) {
+    if (!bh) return fail(MPMC_EINVAL, "NULL box");
+    Box *b = B(bh);
+    uint32_t f = 0;
+    if (b->meas_stream) {
+        if (b->async_fail) {
+            HIPCHK(hipMemcpyAsync(&f, b->async_fail, 4, hipMemcpyDeviceToHost, b->meas_stream));
+            HIPCHK(hipMemsetAsync(b->async_fail, 0, 4, b->meas_stream));
+        }
+        HIPCHK(hipStreamSynchronize(b->meas_stream));
+    }
+    b->meas_pending = false;
+    if (failed) *failed = f;
     return MPMC_OK;
 }
 
@@ -337,6 +421,7 @@ const char kMagic[8] = {'M', 'P', 'M', 'C', 'C', 'K', 'P', '1'};
 extern "C" int mpmc_save(mpmc_box bh, const char *path) {
     if (!bh || !path) return fail(MPMC_EINVAL, "NULL argument");
     Box *b = B(bh);
+    if (int jrc = b->join_meas()) return jrc;
     int rc = b->read_scalars();
     if (rc) return rc;
     const size_t nc = (size_t)b->g.M * b->g.M, ns = nc * b->g.CS;

@@ -581,6 +581,18 @@ __global__ void __launch_bounds__(256) k_positions(MeasureView m, long long *X, 
     Y[tg] = ((long long)(cell / M) * m.W + V + m.Sy) % m.Lq;
 }
 
+// Psi_6 = (sum of psi_j) / N into out[0..1] (device).
+__global__ void k_psi_mean(const DevScalars *dev, double inv_n, double *out) {
+    if (threadIdx.x == 0) {
+        out[0] = dev->psi_re * inv_n;
+        out[1] = dev->psi_im * inv_n;
+    }
+}
+
+void launch_psi_mean(const DevScalars *dev, uint32_t N, double *out, hipStream_t st) {
+    k_psi_mean<<<1, 64, 0, st>>>(dev, 1.0 / (double)N, out);
+}
+
 void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st) {
     const uint32_t n = m.M * m.M * m.CS;
     k_positions<<<(n + 255) / 256, 256, 0, st>>>(m, X, Y);

@@ -78,7 +78,16 @@ struct Box {
     FusedShape shape{0, 0};
     bool use_graphs = true;
     uint32_t graph_sweeps = 64;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraphExec_t graph_exec = nullptr;  // all sweeps of a run but the last
+    // Asynchronous measurement: its kernels run on meas_stream and read only
+    // the canonical buffers C; every later write of C, and every other use of
+    // the measurement buffers, first waits for ev_meas on the box's stream.
+    hipStream_t meas_stream = nullptr;
+    hipEvent_t ev_swept = nullptr, ev_meas = nullptr;
+    bool meas_pending = false;
+    uint32_t *async_fail = nullptr;  // OR of the neighbour-search failures since the last wait
+    int join_meas();                 // orders the box's stream after a pending measurement
+    int measure_async(double *Psi_dev, bool field);
     uint64_t graph_key = 0;
     uint64_t host_sweeps = 0;
     bool in_batch = false;  // owned by a batch: swept and freed by it

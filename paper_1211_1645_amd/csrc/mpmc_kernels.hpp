@@ -82,6 +82,8 @@ void launch_psi6_field(const MeasureView &m, const float *re, const float *im, f
                        float *fim, hipStream_t st);
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);
 void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st);
+// out[0..1] = (psi_re, psi_im) / N from the device sums
+void launch_psi_mean(const DevScalars *dev, uint32_t N, double *out, hipStream_t st);
 
 // Positional order.  Structure factor at nq wave vectors (2 pi / L)(h, k)
 // (device hk[2 nq], S[nq]); work: rho_work_bytes(m, nq) bytes.

@@ -70,6 +70,8 @@ _SIGS = {
     "mpmc_contact_hist_subset": [_P, _P, _P],
     "mpmc_psi6_field": [_P, _P, _P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int],
     "mpmc_get_positions": [_P, _P, _P, _P, _P],
+    "mpmc_measure_async": [_P, _P, C.c_int],
+    "mpmc_measure_wait": [_P, C.POINTER(C.c_uint32)],
     "mpmc_structure_factor": [_P, _P, C.c_uint32, _P],
     "mpmc_find_q0": [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32), C.POINTER(C.c_double)],
@@ -316,6 +318,24 @@ class Box:
         r, i = C.c_double(), C.c_double()
         _check(_lib.mpmc_psi6_field(self.h, None, None, None, None, C.byref(r), C.byref(i), 0))
         return complex(r.value, i.value)
+
+    def measure_async(self, psi_out=None, field=False):
+        """Contact histogram and psi_6 on the box's measurement stream,
+        overlapping the next sweeps; psi_out: a float64 CUDA tensor of two
+        elements that receives Psi_6 (re, im)."""
+        ptr = None
+        if psi_out is not None:
+            assert psi_out.is_cuda and psi_out.dtype.is_floating_point and psi_out.numel() >= 2
+            assert psi_out.element_size() == 8 and psi_out.is_contiguous()
+            ptr = C.c_void_p(psi_out.data_ptr())
+        _check(_lib.mpmc_measure_async(self.h, ptr, 1 if field else 0))
+
+    def measure_wait(self):
+        """Waits for the asynchronous measurements; True if a neighbour
+        search among them was too short."""
+        f = C.c_uint32()
+        _check(_lib.mpmc_measure_wait(self.h, C.byref(f)))
+        return bool(f.value)
 
     # ---- positional order (Sec. IV.D) --------------------------------------
     def wave_vector(self, h, k):
