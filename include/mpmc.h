@@ -256,7 +256,7 @@ int mpmc_power_law(const double *x, const double *y, uint32_t n, double *exponen
 
 /* Asynchronous measurement of the current configuration: adds it to the
  * contact histogram (as mpmc_accumulate_contacts) and evaluates psi_6 (as
- * mpmc_psi6_field, with the stencil half-width of its first attempt) on a
+ * mpmc_psi6_field, with the widest staged stencil, 3 cells) on a
  * stream of the box's own, so that the kernels overlap the sweeps that
  * follow; nothing is copied to the host.  Psi (may be NULL): device pointer
  * to two doubles that receive the global Psi_6 (re, im) once the kernels

@@ -284,6 +284,8 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
 // the box's own, so that they overlap the sweeps that follow: the kernels
 // read the canonical state C, which the next run of sweeps overwrites only in
 // its last sweep, after waiting for them.
+constexpr int kAsyncPsiHalo = 3;
+
 int Box::measure_async(double *Psi_dev, bool field) {
     if (in_batch) return fail(MPMC_ESTATE, "a batch box is measured through its batch");
     if (N < 7) return fail(MPMC_EINVAL, "psi_6 needs at least 7 disks");
@@ -291,8 +293,10 @@ int Box::measure_async(double *Psi_dev, bool field) {
     const uint32_t K = p.hist_bins;
     const double rmax = 2.0 + K * p.hist_dr;
     const uint32_t hc = ((double)g.w >= rmax) ? 1u : 2u;
+    // the widest staged stencil (mpmc_psi6_field's last attempt): nothing
+    // can be retried here, and a wider stencil finds the same six nearest
     const uint32_t hmax = (g.M - 2) / 2;
-    const uint32_t hp = hmax < 2 ? hmax : 2;
+    const uint32_t hp = hmax < (uint32_t)kAsyncPsiHalo ? hmax : (uint32_t)kAsyncPsiHalo;
     if (hp < 1 || !measure_tiled(mview(), hc) || !measure_tiled(mview(), hp))
         return fail(MPMC_EINVAL, "asynchronous measurement needs the staged kernels (cells of at most 4 disks, a box of at least 6 cells)");
     int rc = materialize();  // the kernels read C
