@@ -105,6 +105,21 @@ def stored_tau():
     return out
 
 
+def stored_pressure():
+    """The pressure measured by `--workload pressure` at the paper's test
+    point (N = 256^2, eta = 0.698, Table I), from its committed summary, or
+    None."""
+    path = os.path.join(ROOT, "profiles", "pressure_256sq_eta0698.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    out = {k: d.get(k) for k in ("p_star", "se", "paper_p_star", "paper_se", "z_vs_paper",
+                                 "displacements_per_run", "command")}
+    out["N"], out["eta"], out["replicas"] = 256 * 256, 0.698, d["config"]["replicas"]
+    out["source"] = "profiles/pressure_256sq_eta0698.json"
+    return out
+
+
 def copy_calibration(nbytes=512 << 20, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -509,6 +524,86 @@ def tau_bench(args):
     print(json.dumps(line))
 
 
+PRESSURE_N, PRESSURE_ETA = 256 * 256, 0.698
+PRESSURE_PAPER = (9.17078, 4.5e-5)   # MPMC pressure and standard error (Table I)
+
+
+def pressure_bench(args):
+    """The pressure at the paper's test point (N = 256^2, eta = 0.698, Table
+    I): independent replicas from triangular starts (Philox keys seed + 100 +
+    r) swept together as one batch, the contact histogram accumulated every
+    `p_sample` sweeps and fitted per replica and block of `p_block` sweeps;
+    blocks that end within the first `p_equil` sweeps are dropped.  The
+    standard error comes from the scatter of the replica means."""
+    import numpy as np
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    R = args.p_replicas
+    tb = mp.Box(PRESSURE_N, PRESSURE_ETA, seed=args.seed + 99, step_m=20)
+    step_m, _ = tune_step(tb)
+    tb.close()
+    seeds = np.arange(args.seed + 100, args.seed + 100 + R, dtype=np.uint64)
+    b = mp.Batch(np.full(R, PRESSURE_N, np.uint32), np.full(R, PRESSURE_ETA), seeds, step_m=step_m)
+    b.set_graphs(args.p_sample)
+    boxes = [b.box(i) for i in range(R)]
+    inf = b.info()
+    progress("pressure run: %d replicas of N=%d, eta=%.3f, m=%d, tile %d" %
+             (R, PRESSURE_N, PRESSURE_ETA, step_m, inf["tile"]))
+    n_blocks = (args.p_equil + args.p_sweeps) // args.p_block
+    per_block = args.p_block // args.p_sample
+    P = np.zeros((n_blocks, R))
+    trials = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = t0
+    for blk in range(n_blocks):
+        for bx in boxes:
+            bx.reset_contacts()
+        for _ in range(per_block):
+            t, _a = b.sweep(args.p_sample, counts=True)
+            trials += t
+            b.accumulate_contacts()
+        P[blk] = b.measure_pressure()[0]
+        now = time.perf_counter()
+        if now - last > 20.0 or blk == n_blocks - 1:
+            progress("pressure run: %d of %d sweeps, block mean P* = %.5f" %
+                     ((blk + 1) * args.p_block, n_blocks * args.p_block, P[blk].mean()))
+            last = now
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    keep = P[args.p_equil // args.p_block:]
+    rep = keep.mean(axis=0)
+    mean = float(rep.mean())
+    se = float(rep.std(ddof=1) / math.sqrt(R))
+    paper, paper_se = PRESSURE_PAPER
+    sweeps = n_blocks * args.p_block
+    line = {
+        "metric": "P* = beta P (2 sigma)^2 at N=256^2, eta=0.698 (Table I)",
+        "value": mean, "unit": "dimensionless",
+        "n_gpus": 1, "steps": n_blocks, "warmup": 0,
+        "ms_per_step": elapsed / n_blocks * 1e3,
+        "higher_is_better": None, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (triangular starts, Philox4x32-10 seeds %d..%d)" %
+                (args.seed + 100, args.seed + 99 + R),
+        "config": {"workload": "%d independent replicas of N=256^2 at eta=0.698 in one batch, "
+                               "step tuned to ~30%% acceptance (m=%d); %d sweeps each, contact "
+                               "histogram every %d sweeps, blocks of %d sweeps, first %d "
+                               "sweeps discarded" %
+                               (R, step_m, sweeps, args.p_sample, args.p_block, args.p_equil),
+                   "N": PRESSURE_N, "eta": PRESSURE_ETA, "replicas": R,
+                   "hist_bins": 100, "hist_dr_sigma": 1e-3, "fit_order": 4},
+        "p_star": mean, "se": se,
+        "paper_p_star": paper, "paper_se": paper_se,
+        "z_vs_paper": (mean - paper) / math.sqrt(se * se + paper_se * paper_se),
+        "replica_means": rep.tolist(),
+        "block_means": P.mean(axis=1).tolist(),
+        "displacements_per_run": trials / R,
+        "trial_moves_per_s": trials / elapsed,
+        "seconds": elapsed,
+    }
+    print(json.dumps(line))
+
+
 def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
     """The oracle (single thread) on the same start and step: sweeps of the
     full 1024^2 box until about target_seconds of CPU work."""
@@ -543,15 +638,22 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "positional", "tau", "scale", "batch"),
+    ap.add_argument("--workload",
+                    choices=("sweep", "positional", "tau", "scale", "batch", "pressure"),
                     default="sweep",
                     help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
                          "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes); "
-                         "scale: the sweep at N=4096^2; batch: 64 boxes in one launch")
+                         "scale: the sweep at N=4096^2; batch: 64 boxes in one launch; "
+                         "pressure: P* at N=256^2, eta=0.698 over replicas (minutes)")
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
     ap.add_argument("--tau-discard", type=int, default=4000000)
     ap.add_argument("--tau-sample", type=int, default=1000)
     ap.add_argument("--tau-series", default="", help="save the Psi6 series (.npy)")
+    ap.add_argument("--p-replicas", type=int, default=16)
+    ap.add_argument("--p-equil", type=int, default=2000000)
+    ap.add_argument("--p-sweeps", type=int, default=4000000)
+    ap.add_argument("--p-block", type=int, default=250000)
+    ap.add_argument("--p-sample", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -578,6 +680,9 @@ def main():
         return
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "pressure":
+        pressure_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -656,6 +761,7 @@ def main():
         "trials_per_sweep": trials_per_sweep,
         "psi6_decorrelations_per_s": None,
         "psi6_tau_at_paper_point": stored_tau(),
+        "pressure_at_paper_point": stored_pressure(),
         "P_star_sample": pressure["P_star"],
         "abs_Psi6_mean": sum(abs(p) for p in psi_series) / len(psi_series),
         "validate": {"overlaps": overlaps, "bad": bad},

@@ -43,3 +43,21 @@ def test_stored_profiles_are_readable():
     # the traffic figure is reported only for the kernel source it was taken on
     t = bench.stored_traffic()
     assert t is None or t > bench.algorithmic_bytes_per_sweep(1024 * 1024, 1072)
+
+
+def test_stored_pressure_agrees_with_table_one():
+    """The committed pressure run at N = 256^2, eta = 0.698 against the
+    paper's MPMC value (Table I): its own replica error, recomputed from the
+    stored replica means, and agreement within three combined errors."""
+    import json
+    import math
+    import os
+    p = bench.stored_pressure()
+    assert p is not None and p["paper_p_star"] == 9.17078 and p["replicas"] >= 8
+    d = json.load(open(os.path.join(bench.ROOT, p["source"])))
+    rep = d["replica_means"]
+    mean = sum(rep) / len(rep)
+    sd = math.sqrt(sum((x - mean) ** 2 for x in rep) / (len(rep) - 1))
+    assert mean == pytest.approx(p["p_star"], abs=1e-12)
+    assert sd / math.sqrt(len(rep)) == pytest.approx(p["se"], rel=1e-9)
+    assert abs(p["p_star"] - 9.17078) < 3 * math.hypot(p["se"], 4.5e-5)
