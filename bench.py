@@ -528,6 +528,36 @@ PRESSURE_N, PRESSURE_ETA = 256 * 256, 0.698
 PRESSURE_PAPER = (9.17078, 4.5e-5)   # MPMC pressure and standard error (Table I)
 
 
+def batch_pressure_blocks(b, n_blocks, block, sample, label):
+    """P* of every box of batch `b` for each of `n_blocks` blocks of `block`
+    sweeps, the contact histogram accumulated every `sample` sweeps and reset
+    at the start of each block: (P[block, box], trial moves, seconds)."""
+    import numpy as np
+    import torch
+    boxes = [b.box(i) for i in range(b.n)]
+    per_block = block // sample
+    P = np.zeros((n_blocks, b.n))
+    trials = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = t0
+    for blk in range(n_blocks):
+        for bx in boxes:
+            bx.reset_contacts()
+        for _ in range(per_block):
+            t, _a = b.sweep(sample, counts=True)
+            trials += t
+            b.accumulate_contacts()
+        P[blk] = b.measure_pressure()[0]
+        now = time.perf_counter()
+        if now - last > 20.0 or blk == n_blocks - 1:
+            progress("%s: %d of %d sweeps, block mean P* = %.5f" %
+                     (label, (blk + 1) * block, n_blocks * block, P[blk].mean()))
+            last = now
+    torch.cuda.synchronize()
+    return P, trials, time.perf_counter() - t0
+
+
 def pressure_bench(args):
     """The pressure at the paper's test point (N = 256^2, eta = 0.698, Table
     I): independent replicas from triangular starts (Philox keys seed + 100 +
@@ -545,32 +575,12 @@ def pressure_bench(args):
     seeds = np.arange(args.seed + 100, args.seed + 100 + R, dtype=np.uint64)
     b = mp.Batch(np.full(R, PRESSURE_N, np.uint32), np.full(R, PRESSURE_ETA), seeds, step_m=step_m)
     b.set_graphs(args.p_sample)
-    boxes = [b.box(i) for i in range(R)]
     inf = b.info()
     progress("pressure run: %d replicas of N=%d, eta=%.3f, m=%d, tile %d" %
              (R, PRESSURE_N, PRESSURE_ETA, step_m, inf["tile"]))
     n_blocks = (args.p_equil + args.p_sweeps) // args.p_block
-    per_block = args.p_block // args.p_sample
-    P = np.zeros((n_blocks, R))
-    trials = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    last = t0
-    for blk in range(n_blocks):
-        for bx in boxes:
-            bx.reset_contacts()
-        for _ in range(per_block):
-            t, _a = b.sweep(args.p_sample, counts=True)
-            trials += t
-            b.accumulate_contacts()
-        P[blk] = b.measure_pressure()[0]
-        now = time.perf_counter()
-        if now - last > 20.0 or blk == n_blocks - 1:
-            progress("pressure run: %d of %d sweeps, block mean P* = %.5f" %
-                     ((blk + 1) * args.p_block, n_blocks * args.p_block, P[blk].mean()))
-            last = now
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    P, trials, elapsed = batch_pressure_blocks(b, n_blocks, args.p_block, args.p_sample,
+                                               "pressure run")
     keep = P[args.p_equil // args.p_block:]
     rep = keep.mean(axis=0)
     mean = float(rep.mean())
@@ -600,6 +610,85 @@ def pressure_bench(args):
         "displacements_per_run": trials / R,
         "trial_moves_per_s": trials / elapsed,
         "seconds": elapsed,
+    }
+    print(json.dumps(line))
+
+
+EOS_ETAS = tuple(round(0.696 + 0.002 * i, 3) for i in range(15))   # 0.696 ... 0.724
+EOS_SIZES = ((128 * 128, 3), (256 * 256, 2))                        # (N, replicas)
+
+
+def eos_bench(args):
+    """Equation of state across the coexistence region (Sec. IV.A): boxes of
+    N = 128^2 and 256^2 at eta = 0.696 ... 0.724 (step 0.002), several
+    replicas each, all swept together as one batch from triangular starts;
+    P* per box and block as in the pressure workload, the first `p_equil`
+    sweeps dropped; then the Mayer-Wood loop analysis of each size (cubic and
+    quintic fits in v = pi / eta) and the exponent of beta Delta f(N)."""
+    import numpy as np
+    import paper_1211_1645_amd.mpmc as mp
+    Ns, etas, seeds = [], [], []
+    for N, R in EOS_SIZES:
+        for e in EOS_ETAS:
+            for r in range(R):
+                Ns.append(N)
+                etas.append(e)
+                seeds.append(args.seed + 200 + len(seeds))
+    tb = mp.Box(256 * 256, 0.710, seed=args.seed + 199, step_m=20)
+    step_m, _ = tune_step(tb)
+    tb.close()
+    b = mp.Batch(np.asarray(Ns, np.uint32), np.asarray(etas), np.asarray(seeds, np.uint64),
+                 step_m=step_m)
+    b.set_graphs(args.p_sample)
+    inf = b.info()
+    progress("eos run: %d boxes, %d disks, m=%d, tile %d" % (b.n, sum(Ns), step_m, inf["tile"]))
+    n_blocks = (args.p_equil + args.p_sweeps) // args.p_block
+    P, trials, elapsed = batch_pressure_blocks(b, n_blocks, args.p_block, args.p_sample, "eos run")
+    keep = P[args.p_equil // args.p_block:].mean(axis=0)
+    Ns, etas = np.asarray(Ns), np.asarray(etas)
+    sizes = []
+    for N, R in EOS_SIZES:
+        p, se = [], []
+        for e in EOS_ETAS:
+            v = keep[(Ns == N) & (etas == e)]
+            p.append(float(v.mean()))
+            se.append(float(v.std(ddof=1) / math.sqrt(len(v))))
+        loops = {}
+        for order in (3, 5):
+            try:
+                loops["order%d" % order] = mp.eos_loop(np.asarray(EOS_ETAS), np.asarray(p),
+                                                       order=order)
+            except mp.MPMCError as err:
+                loops["order%d" % order] = {"error": str(err)}
+        sizes.append({"N": int(N), "replicas": R, "eta": list(EOS_ETAS), "p_star": p, "se": se,
+                      "loop": loops})
+        progress("eos N=%d: %s" % (N, " ".join("%.4f" % x for x in p)))
+    expo = {}
+    for order in ("order3", "order5"):
+        df = [sz["loop"][order].get("delta_f") for sz in sizes]
+        if all(x is not None and x > 0 for x in df):
+            expo[order] = mp.power_law(np.asarray([sz["N"] for sz in sizes], np.float64),
+                                       np.asarray(df))[0]
+    sweeps = n_blocks * args.p_block
+    line = {
+        "metric": "equation of state P*(eta) and Mayer-Wood loop, N=128^2 and 256^2",
+        "value": trials / elapsed, "unit": "trial moves/s",
+        "n_gpus": 1, "steps": n_blocks, "warmup": 0,
+        "ms_per_step": elapsed / n_blocks * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (triangular starts, Philox4x32-10 seeds %d..%d)" %
+                (args.seed + 200, args.seed + 199 + b.n),
+        "config": {"workload": "%d boxes (N=128^2 x3 and 256^2 x2 replicas at 15 densities "
+                               "0.696-0.724) in one batch, m=%d; %d sweeps each, contact "
+                               "histogram every %d sweeps, blocks of %d sweeps, first %d "
+                               "discarded" % (b.n, step_m, sweeps, args.p_sample, args.p_block,
+                                              args.p_equil),
+                   "boxes": b.n, "disks": int(Ns.sum())},
+        "sizes": sizes,
+        "delta_f_exponent": expo,
+        "paper_extrema_eta": [0.702, 0.714],
+        "seconds": elapsed,
+        "block_P": P.tolist(),
     }
     print(json.dumps(line))
 
@@ -639,12 +728,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workload",
-                    choices=("sweep", "positional", "tau", "scale", "batch", "pressure"),
+                    choices=("sweep", "positional", "tau", "scale", "batch", "pressure", "eos"),
                     default="sweep",
                     help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
                          "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes); "
                          "scale: the sweep at N=4096^2; batch: 64 boxes in one launch; "
-                         "pressure: P* at N=256^2, eta=0.698 over replicas (minutes)")
+                         "pressure: P* at N=256^2, eta=0.698 over replicas (minutes); "
+                         "eos: P*(eta) and its loop at N=128^2 and 256^2 (minutes)")
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
     ap.add_argument("--tau-discard", type=int, default=4000000)
     ap.add_argument("--tau-sample", type=int, default=1000)
@@ -683,6 +773,9 @@ def main():
         return
     if args.workload == "pressure":
         pressure_bench(args)
+        return
+    if args.workload == "eos":
+        eos_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
