@@ -128,13 +128,19 @@ struct PassCtx {
 // overlap any disk of its 3 x 3 neighbourhood other than slot `slot` of its
 // own cell (whose records are mx, my)?  Only slots below SL are tested: the
 // caller knows that no cell of the region holds more than SL disks, and the
-// empty slots hold the far sentinel.
+// empty slots hold the far sentinel.  In the two-slot form the squared
+// separations of a row of three cells (each rounded as in overlap_f32) are
+// reduced by a running minimum and compared once per row: the minimum is
+// below 4 exactly when one of them is.  The rare four-slot form compares the
+// neighbours' pairs one by one, which holds fewer registers live.
 template <int SL, int H, int CX, int CY, typename LdsT>
 __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_t slot,
                                              const float4 &mx, const float4 &my, float xn,
                                              float yn, float w) {
     const float ax3[3] = {xn + w, xn, xn - w};  // q_di = s' - di w
     const float ay3[3] = {yn + w, yn, yn - w};
+    constexpr float kNone = 16.0f;  // stands for a pair that is not tested
+    float dmin = kNone;
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -142,34 +148,38 @@ __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_
         const float gx = ax3[k % 3], gy = ay3[k / 3];
         if (k == 4) {
             // own cell: every slot but the moving one
-            bad |= slot != 0 && overlap_f32(mx.x - gx, my.x - gy);
-            bad |= slot != 1 && overlap_f32(mx.y - gx, my.y - gy);
+            dmin = fminf(dmin, slot != 0 ? r2_f32(mx.x - gx, my.x - gy) : kNone);
+            dmin = fminf(dmin, slot != 1 ? r2_f32(mx.y - gx, my.y - gy) : kNone);
             if (SL > 2) {
-                bad |= slot != 2 && overlap_f32(mx.z - gx, my.z - gy);
-                bad |= slot != 3 && overlap_f32(mx.w - gx, my.w - gy);
+                dmin = fminf(dmin, slot != 2 ? r2_f32(mx.z - gx, my.z - gy) : kNone);
+                dmin = fminf(dmin, slot != 3 ? r2_f32(mx.w - gx, my.w - gy) : kNone);
             }
-            continue;
-        }
-        // neighbour (rx + di, ry + dj): its colour plane and in-plane offset
-        // are compile-time constants for this colour
-        const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
-        const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
-        const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
-        if (SL > 2) {
-            const float4 qx = L.x[ne], qy = L.y[ne];
-            bad |= overlap_f32(qx.x - gx, qy.x - gy);
-            bad |= overlap_f32(qx.y - gx, qy.y - gy);
-            bad |= overlap_f32(qx.z - gx, qy.z - gy);
-            bad |= overlap_f32(qx.w - gx, qy.w - gy);
         } else {
-            const float2 qx = *reinterpret_cast<const float2 *>(&L.x[ne]);
-            const float2 qy = *reinterpret_cast<const float2 *>(&L.y[ne]);
-            bad |= overlap_f32(qx.x - gx, qy.x - gy);
-            bad |= overlap_f32(qx.y - gx, qy.y - gy);
+            // neighbour (rx + di, ry + dj): its colour plane and in-plane
+            // offset are compile-time constants for this colour
+            const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
+            const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
+            const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
+            if (SL > 2) {
+                const float4 qx = L.x[ne], qy = L.y[ne];
+                bad |= overlap_f32(qx.x - gx, qy.x - gy);
+                bad |= overlap_f32(qx.y - gx, qy.y - gy);
+                bad |= overlap_f32(qx.z - gx, qy.z - gy);
+                bad |= overlap_f32(qx.w - gx, qy.w - gy);
+            } else {
+                const float2 qx = *reinterpret_cast<const float2 *>(&L.x[ne]);
+                const float2 qy = *reinterpret_cast<const float2 *>(&L.y[ne]);
+                dmin = fminf(dmin, r2_f32(qx.x - gx, qy.x - gy));
+                dmin = fminf(dmin, r2_f32(qx.y - gx, qy.y - gy));
+            }
         }
-        // one row of neighbour records in flight at a time keeps the
-        // register budget of four waves per SIMD
-        if (k == 2 || k == 5) __asm__ volatile("" ::: "memory");
+        if (k % 3 == 2) {
+            bad |= dmin < 4.0f;
+            dmin = kNone;
+            // one row of neighbour records in flight at a time keeps the
+            // register budget of four waves per SIMD
+            __asm__ volatile("" ::: "memory");
+        }
     }
     return bad;
 }
