@@ -298,7 +298,7 @@ def positional_bench(args):
         line["cpu_baseline"] = dict(
             value=nq * float(info["N"]) / dt, unit="terms/s", cores=1, kind="oracle",
             sample="S(q) at %d of the same wave vectors on the oracle's N=1024^2 box after one "
-                   "sweep (%.1f s, 1 thread)" % (nq, dt))
+                   "sweep (%.1f s, 1 thread of %s)" % (nq, dt, host_cpu()))
     print(json.dumps(line))
 
 
@@ -710,8 +710,21 @@ def cpu_baseline(start_sweeps, seed, step_m, target_seconds=15.0):
     return dict(value=(i1["trials"] - i0["trials"]) / dt, unit="trial moves/s", cores=1,
                 kind="oracle",
                 sample="%d sweeps of the N=1024^2 eta=0.716 box after 1 from the same "
-                       "triangular start (%.1f s, 1 thread, %s)" % (k, dt, platform.processor() or
-                                                                     platform.machine()))
+                       "triangular start (%.1f s, 1 thread of %s)" % (k, dt, host_cpu()),
+                build="gcc -O2 -ffp-contract=off -fno-fast-math")
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host, from /proc/cpuinfo."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs" % (model, os.cpu_count() or 0)
 
 
 def progress(msg):
