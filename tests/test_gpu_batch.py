@@ -51,7 +51,7 @@ def test_batch_schedules_agree(gpu_lib):
             assert same_cells(bt.box(i), ref.box(i)), (tile, threads, i)
 
 
-def test_config4_batch_of_64(gpu_lib):
+def test_batch_of_64_uneven_boxes(gpu_lib):
     N, eta, seed = batch_boxes(nbox=64, seed=0)
     bt = gpu_lib.Batch(N, eta, seed, step_m=40, hist_bins=100, hist_dr=1e-3)
     info = bt.info()

@@ -17,8 +17,8 @@ from oracle.orc import OracleBox
 
 pytestmark = pytest.mark.gpu
 
-CONFIG1 = dict(N=256, eta=0.60, seed=0, lattice=0, step_m=26)
-CONFIG2 = dict(N=65536, eta=0.716, seed=0, lattice=1, step_m=20)
+SQUARE_256 = dict(N=256, eta=0.60, seed=0, lattice=0, step_m=26)
+TRI_65536 = dict(N=65536, eta=0.716, seed=0, lattice=1, step_m=20)
 
 
 def gpu_box(mp, N, eta, seed, lattice, step_m, n_trial=1, **kw):
@@ -43,10 +43,10 @@ def assert_same_state(g, o):
 
 
 @pytest.mark.parametrize("schedule,tile,threads", [("simple", 0, 0), ("fused", 8, 64), ("fused", 8, 128)])
-def test_config1_trajectory_bit_exact(gpu_lib, schedule, tile, threads):
-    g = gpu_box(gpu_lib, **CONFIG1, schedule="simple")
+def test_n256_square_start_trajectory_bit_exact(gpu_lib, schedule, tile, threads):
+    g = gpu_box(gpu_lib, **SQUARE_256, schedule="simple")
     g.set_schedule(schedule, tile, threads)
-    o = OracleBox(**CONFIG1)
+    o = OracleBox(**SQUARE_256)
     assert_same_state(g, o)
     done = 0
     for k in (1, 10, 100, 1000):
@@ -60,8 +60,8 @@ def test_config1_trajectory_bit_exact(gpu_lib, schedule, tile, threads):
 @pytest.mark.parametrize("n_trial", [2, 4])
 def test_shuffled_trials_bit_exact(gpu_lib, n_trial):
     for schedule, tile in (("simple", 0), ("fused", 8)):
-        g = gpu_box(gpu_lib, **CONFIG1, n_trial=n_trial, schedule=schedule, tile=tile)
-        o = OracleBox(**CONFIG1, n_trial=n_trial)
+        g = gpu_box(gpu_lib, **SQUARE_256, n_trial=n_trial, schedule=schedule, tile=tile)
+        o = OracleBox(**SQUARE_256, n_trial=n_trial)
         g.sweep(57)
         o.sweep(57)
         assert_same_state(g, o)
@@ -88,10 +88,10 @@ def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
     assert g.validate() == (0, 0)
 
 
-def test_config2_trajectory_bit_exact(gpu_lib):
-    g = gpu_box(gpu_lib, **CONFIG2)  # autotuned fused schedule
+def test_n65536_triangular_trajectory_bit_exact(gpu_lib):
+    g = gpu_box(gpu_lib, **TRI_65536)  # autotuned fused schedule
     assert g.info()["schedule"] == 2
-    o = OracleBox(**CONFIG2)
+    o = OracleBox(**TRI_65536)
     done = 0
     for k in (1, 10, 60):
         g.sweep(k - done)
@@ -104,13 +104,13 @@ def test_config2_trajectory_bit_exact(gpu_lib):
 def test_schedule_invariance_all_shapes(gpu_lib):
     """Every schedule (simple, each fused tile/threads shape, graphs on or
     off) gives the same trajectory."""
-    ref = gpu_box(gpu_lib, **CONFIG2, schedule="simple")
+    ref = gpu_box(gpu_lib, **TRI_65536, schedule="simple")
     ref.sweep(20)
     rc = ref.cells()
     shapes = [(8, 64), (8, 128), (16, 128), (16, 256), (24, 256), (32, 256), (32, 512),
               (48, 512), (48, 1024)]
     for tile, threads in shapes:
-        b = gpu_box(gpu_lib, **CONFIG2, schedule="simple")
+        b = gpu_box(gpu_lib, **TRI_65536, schedule="simple")
         b.set_schedule("fused", tile, threads)
         b.set_graphs(0 if tile == 24 else 4)
         b.sweep(20)
@@ -119,8 +119,8 @@ def test_schedule_invariance_all_shapes(gpu_lib):
 
 
 def test_graph_replay_matches_eager(gpu_lib):
-    a = gpu_box(gpu_lib, **CONFIG1, schedule="fused", tile=8)
-    b = gpu_box(gpu_lib, **CONFIG1, schedule="fused", tile=8)
+    a = gpu_box(gpu_lib, **SQUARE_256, schedule="fused", tile=8)
+    b = gpu_box(gpu_lib, **SQUARE_256, schedule="fused", tile=8)
     b.set_graphs(0)
     a.sweep(3)          # odd start: eager sweeps until the buffers line up
     a.sweep(300)        # graph replays of 128 sweeps
@@ -133,7 +133,7 @@ def test_graph_replay_matches_eager(gpu_lib):
 
 
 def test_checkpoint_resume_bit_exact(gpu_lib, tmp_path):
-    a = gpu_box(gpu_lib, **CONFIG1)
+    a = gpu_box(gpu_lib, **SQUARE_256)
     a.sweep(50)
     a.accumulate_contacts()
     path = str(tmp_path / "ck.bin")
@@ -148,8 +148,8 @@ def test_checkpoint_resume_bit_exact(gpu_lib, tmp_path):
 
 
 def test_contact_histogram_counts_identical(gpu_lib):
-    g = gpu_box(gpu_lib, **CONFIG1, hist_bins=20, hist_dr=0.01)
-    o = OracleBox(**CONFIG1)
+    g = gpu_box(gpu_lib, **SQUARE_256, hist_bins=20, hist_dr=0.01)
+    o = OracleBox(**SQUARE_256)
     oc = np.zeros(20, np.int64)
     for _ in range(5):
         g.sweep(37)
@@ -164,9 +164,9 @@ def test_contact_histogram_counts_identical(gpu_lib):
     assert abs(res["g_contact"] - ref["g_contact"]) < 1e-10 * ref["g_contact"]
 
 
-def test_contact_histogram_config2_default_bins(gpu_lib):
-    g = gpu_box(gpu_lib, **CONFIG2)
-    o = OracleBox(**CONFIG2)
+def test_contact_histogram_n65536_default_bins(gpu_lib):
+    g = gpu_box(gpu_lib, **TRI_65536)
+    o = OracleBox(**TRI_65536)
     g.sweep(30)
     o.sweep(30)
     g.accumulate_contacts()
@@ -177,8 +177,8 @@ def test_contact_histogram_config2_default_bins(gpu_lib):
 
 
 def test_psi6_matches_oracle(gpu_lib):
-    g = gpu_box(gpu_lib, **CONFIG1)
-    o = OracleBox(**CONFIG1)
+    g = gpu_box(gpu_lib, **SQUARE_256)
+    o = OracleBox(**SQUARE_256)
     g.sweep(200)
     o.sweep(200)
     psi, field, Psi = g.psi6_field()
@@ -189,10 +189,10 @@ def test_psi6_matches_oracle(gpu_lib):
     assert np.abs(field - ofield).max() < 1e-5
 
 
-def test_psi6_config2_matches_oracle(gpu_lib):
+def test_psi6_n65536_matches_oracle(gpu_lib):
     """Many 16 x 16 cell blocks (M = 226) of the tiled psi_6 kernel."""
-    g = gpu_box(gpu_lib, **CONFIG2)
-    o = OracleBox(**CONFIG2)
+    g = gpu_box(gpu_lib, **TRI_65536)
+    o = OracleBox(**TRI_65536)
     g.sweep(40)
     o.sweep(40)
     psi, field, Psi = g.psi6_field()
@@ -204,7 +204,7 @@ def test_psi6_config2_matches_oracle(gpu_lib):
 
 def test_fused_tiles_must_not_wrap(gpu_lib):
     """A tile whose halo region would cover the box twice is refused."""
-    g = gpu_box(gpu_lib, **CONFIG1, schedule="simple")
+    g = gpu_box(gpu_lib, **SQUARE_256, schedule="simple")
     with pytest.raises(gpu_lib.MPMCError):
         g.set_schedule("fused", 16, 256)   # 16 + 10 > M = 18
 
