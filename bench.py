@@ -105,6 +105,21 @@ def stored_tau():
     return out
 
 
+def stored_tau_bound():
+    """The Psi_6 correlation run at the benchmark's own point (N = 1024^2,
+    eta = 0.716), from its committed summary, or None: a lower bound on tau,
+    since the ordered box keeps its orientation through the run."""
+    path = os.path.join(ROOT, "profiles", "psi6_tau_1024sq_eta0716.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    out = {k: d.get(k) for k in ("tau_sweeps_lower_bound", "decorrelations_per_s_upper_bound",
+                                 "abs_Psi6_mean_after_discard", "orientation_drift_deg",
+                                 "command")}
+    out["source"] = "profiles/psi6_tau_1024sq_eta0716.json"
+    return out
+
+
 def stored_pressure():
     """The pressure measured by `--workload pressure` at the paper's test
     point (N = 256^2, eta = 0.698, Table I), from its committed summary, or
@@ -302,7 +317,7 @@ def positional_bench(args):
     print(json.dumps(line))
 
 
-TAU_N, TAU_ETA = 512 * 512, 0.698
+TAU_ETA = 0.698
 TAU_PAPER_DISP = 8.0e5   # MPMC correlation time of Psi_6 in displacements per disk (Table II)
 
 
@@ -460,8 +475,9 @@ def tau_analysis(series, sample, disp_per_sweep, discard):
 
 
 def tau_bench(args):
-    """Psi_6 correlation time of the plain sampler at the configuration of the
-    paper's speed comparison (N = 512^2, eta = 0.698, Table II): a long run
+    """Psi_6 correlation time of the plain sampler, by default at the
+    configuration of the paper's speed comparison (N = 512^2, eta = 0.698,
+    Table II; --tau-side and --tau-eta choose another box): a long run
     from the triangular start, Psi_6 every `sample` sweeps (one graph replay
     each), the first `discard` sweeps dropped, C(dt) of Eq. (9) over all time
     origins, tau from the exponential tail (Sec. III)."""
@@ -471,13 +487,13 @@ def tau_bench(args):
     sample = args.tau_sample
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        box = mp.Box(TAU_N, TAU_ETA, seed=args.seed, step_m=20, lattice="triangular",
-                     stream=stream.cuda_stream)
+        box = mp.Box(args.tau_side ** 2, args.tau_eta, seed=args.seed, step_m=20,
+                     lattice="triangular", stream=stream.cuda_stream)
         box.set_graphs(sample)
         step_m, acc = tune_step(box)
         info = box.info()
         progress("tau run: N=%d eta=%.3f m=%d schedule %d tile %d" %
-                 (info["N"], TAU_ETA, step_m, info["schedule"], info["tile"]))
+                 (info["N"], args.tau_eta, step_m, info["schedule"], info["tile"]))
         n_samples = args.tau_sweeps // sample
         series = np.zeros(n_samples, np.complex128)
         i0 = box.info()
@@ -491,6 +507,8 @@ def tau_bench(args):
             if now - last > 30.0:
                 progress("tau run: %d of %d sweeps, |Psi6| = %.3f" %
                          ((k + 1) * sample, n_samples * sample, abs(series[k])))
+                if args.tau_series:  # the series so far, in case the run is cut short
+                    np.save(args.tau_series, series[:k + 1])
                 last = now
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -500,8 +518,12 @@ def tau_bench(args):
     disp_per_sweep = (i1["trials"] - i0["trials"]) / (n_samples * sample) / info["N"]
     res = tau_analysis(series, sample, disp_per_sweep, args.tau_discard)
     sweeps_per_s = n_samples * sample / elapsed
+    paper_point = (args.tau_side, args.tau_eta) == (512, TAU_ETA)
+    where = ("plain MPMC at the paper's speed-comparison point, N=512^2, eta=0.698"
+             if paper_point else "plain MPMC, N=%d^2, eta=%.3f" % (args.tau_side, args.tau_eta))
     line = {
-        "metric": "psi6-decorrelation sweeps/s (sweeps/s / tau), 512^2 disks eta=0.698",
+        "metric": "psi6-decorrelation sweeps/s (sweeps/s / tau), %d^2 disks eta=%.3f" %
+                  (args.tau_side, args.tau_eta),
         "value": sweeps_per_s * disp_per_sweep / res["tau_efold_displacements_per_disk"],
         "unit": "decorrelations/s",
         "n_gpus": 1, "steps": n_samples, "warmup": 0,
@@ -509,16 +531,15 @@ def tau_bench(args):
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (triangular start, Philox4x32-10 seed %d)" % args.seed,
-        "config": {"workload": "plain MPMC at the paper's speed-comparison point, N=512^2, "
-                               "eta=0.698, step tuned to ~30%% acceptance (m=%d); %d sweeps, "
+        "config": {"workload": "%s, step tuned to ~30%% acceptance (m=%d); %d sweeps, "
                                "Psi6 every %d, first %d discarded" %
-                               (step_m, n_samples * sample, sample, args.tau_discard),
-                   "N": info["N"], "eta": TAU_ETA, "M": info["M"], "tile": info["tile"]},
+                               (where, step_m, n_samples * sample, sample, args.tau_discard),
+                   "N": info["N"], "eta": args.tau_eta, "M": info["M"], "tile": info["tile"]},
         "sweeps_per_s": sweeps_per_s,
         "trial_moves_per_s": (i1["trials"] - i0["trials"]) / elapsed,
         "displacements_per_disk_per_sweep": disp_per_sweep,
         "tau_sweeps": res["tau_sweeps"],
-        "paper_tau_displacements_per_disk": TAU_PAPER_DISP,
+        "paper_tau_displacements_per_disk": TAU_PAPER_DISP if paper_point else None,
     }
     line.update(res)
     print(json.dumps(line))
@@ -748,6 +769,8 @@ def main():
                          "scale: the sweep at N=4096^2; batch: 64 boxes in one launch; "
                          "pressure: P* at N=256^2, eta=0.698 over replicas (minutes); "
                          "eos: P*(eta) and its loop at N=128^2 and 256^2 (minutes)")
+    ap.add_argument("--tau-side", type=int, default=512, help="tau run: N = side^2")
+    ap.add_argument("--tau-eta", type=float, default=TAU_ETA)
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
     ap.add_argument("--tau-discard", type=int, default=4000000)
     ap.add_argument("--tau-sample", type=int, default=1000)
@@ -866,6 +889,7 @@ def main():
         "acceptance": accepts / max(trials, 1),
         "trials_per_sweep": trials_per_sweep,
         "psi6_decorrelations_per_s": None,
+        "psi6_tau_bound_at_this_point": stored_tau_bound(),
         "psi6_tau_at_paper_point": stored_tau(),
         "pressure_at_paper_point": stored_pressure(),
         "P_star_sample": pressure["P_star"],
