@@ -24,20 +24,24 @@ std::map<std::tuple<int, uint32_t, uint32_t>, FusedShape> g_cache;  // (device, 
 static int time_shape(Box *b, const FusedShape &s, int reps, float *ms) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(MPMC_EDEVICE, "hipEventCreate");
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return fail(MPMC_EDEVICE, "hipEventCreate"); }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MPMC_EDEVICE, "hipEventCreate");
+    }
     BoxView v = b->view(b->cur);
     v.cnt_can = nullptr;
     v.x_can = v.y_can = nullptr;
     v.tag_can = nullptr;
     for (int r = 0; r < 3; ++r) launch_fused_sweep(v, s, b->stream);
-    hipEventRecord(e0, b->stream);
-    for (int r = 0; r < reps; ++r) launch_fused_sweep(v, s, b->stream);
-    hipEventRecord(e1, b->stream);
-    hipError_t e = hipEventSynchronize(e1);
+    hipError_t e = hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) launch_fused_sweep(v, s, b->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return fail(MPMC_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
     *ms = t / reps;
     return MPMC_OK;
@@ -45,7 +49,7 @@ static int time_shape(Box *b, const FusedShape &s, int reps, float *ms) {
 
 static int autotune(Box *b, FusedShape *best) {
     int dev = 0;
-    hipGetDevice(&dev);
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MPMC_EDEVICE, "hipGetDevice");
     const auto key = std::make_tuple(dev, b->g.M, b->p.n_trial);
     {
         std::lock_guard<std::mutex> lk(g_mu);

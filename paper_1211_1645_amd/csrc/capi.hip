@@ -103,28 +103,28 @@ void Box::free_dev(void *ptr) {
         if (allocations[i] == ptr) {
             allocations.erase(allocations.begin() + i);
             if (p.alloc) p.free(ptr, p.alloc_ctx);
-            else hipFree(ptr);
+            else (void)hipFree(ptr);
             return;
         }
 }
 
 void Box::release() {
     if (meas_stream) {
-        hipStreamSynchronize(meas_stream);
-        hipStreamDestroy(meas_stream);
+        (void)hipStreamSynchronize(meas_stream);
+        (void)hipStreamDestroy(meas_stream);
         meas_stream = nullptr;
     }
-    if (ev_swept) hipEventDestroy(ev_swept);
-    if (ev_meas) hipEventDestroy(ev_meas);
+    if (ev_swept) (void)hipEventDestroy(ev_swept);
+    if (ev_meas) (void)hipEventDestroy(ev_meas);
     ev_swept = ev_meas = nullptr;
     meas_pending = false;
-    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;
-    if (cap_stream) hipStreamDestroy(cap_stream);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     for (void *a : allocations) {
         if (p.alloc) p.free(a, p.alloc_ctx);
-        else hipFree(a);
+        else (void)hipFree(a);
     }
     allocations.clear();
 }
@@ -390,7 +390,7 @@ int Box::launch_one(int from, uint32_t offset, hipStream_t st, bool canon) {
 
 int Box::build_graph() {
     if (graph_exec) {
-        hipGraphExecDestroy(graph_exec);
+        (void)hipGraphExecDestroy(graph_exec);
         graph_exec = nullptr;
     }
     // the graph holds the first G - 1 sweeps of a run; the last one, which
@@ -403,7 +403,7 @@ int Box::build_graph() {
         launch_one((int)(k & 1u), k, cap_stream, false);
     HIPCHK(hipStreamEndCapture(cap_stream, &graph));
     hipError_t e = hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
         graph_exec = nullptr;
         return fail(MPMC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));

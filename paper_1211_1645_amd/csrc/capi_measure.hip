@@ -219,7 +219,7 @@ extern "C" int mpmc_contact_hist_subset(mpmc_box bh, const uint8_t *sel, int64_t
         for (size_t i = 0; i < b->allocations.size(); ++i)
             if (b->allocations[i] == ptr) {
                 if (b->p.alloc) b->p.free(ptr, b->p.alloc_ctx);
-                else hipFree(ptr);
+                else (void)hipFree(ptr);
                 b->allocations.erase(b->allocations.begin() + i);
                 break;
             }
@@ -293,10 +293,13 @@ int Box::measure_async(double *Psi_dev, bool field) {
     const uint32_t K = p.hist_bins;
     const double rmax = 2.0 + K * p.hist_dr;
     const uint32_t hc = ((double)g.w >= rmax) ? 1u : 2u;
-    // the widest staged stencil (mpmc_psi6_field's last attempt): nothing
-    // can be retried here, and a wider stencil finds the same six nearest
+    // as mpmc_psi6_field: stencil 2 first, then the widest staged stencil,
+    // but the second pass is launched always and decides on the device
+    // whether it has anything to do (a wider stencil finds the same six
+    // nearest, so the result does not depend on which pass produced it)
     const uint32_t hmax = (g.M - 2) / 2;
     const uint32_t hp = hmax < (uint32_t)kAsyncPsiHalo ? hmax : (uint32_t)kAsyncPsiHalo;
+    const uint32_t h1 = hp < 2u ? hp : 2u;
     if (hp < 1 || !measure_tiled(mview(), hc) || !measure_tiled(mview(), hp))
         return fail(MPMC_EINVAL, "asynchronous measurement needs the staged kernels (cells of at most 4 disks, a box of at least 6 cells)");
     int rc = materialize();  // the kernels read C
@@ -308,10 +311,10 @@ int Box::measure_async(double *Psi_dev, bool field) {
         rc = alloc_dev((void **)&psi_buf, (2 * (size_t)N + 2 * nc) * 4);
         if (rc) return rc;
     }
-    if (!async_fail) {
-        rc = alloc_dev((void **)&async_fail, 4);
+    if (!async_fail) {  // [0]: verdict reported by mpmc_measure_wait, [1]: first pass
+        rc = alloc_dev((void **)&async_fail, 8);
         if (rc) return rc;
-        HIPCHK(hipMemsetAsync(async_fail, 0, 4, stream));
+        HIPCHK(hipMemsetAsync(async_fail, 0, 8, stream));
     }
     if (!meas_stream) {
         HIPCHK(hipStreamCreateWithFlags(&meas_stream, hipStreamNonBlocking));
@@ -325,7 +328,12 @@ int Box::measure_async(double *Psi_dev, bool field) {
     HIPCHK(hipGetLastError());
     ++n_conf;
     float *dre = psi_buf, *dim = dre + N, *dfr = dim + N, *dfi = dfr + nc;
-    launch_psi6(m, hp, dre, dim, async_fail, loc, meas_work, meas_stream);
+    if (h1 < hp) {
+        HIPCHK(hipMemsetAsync(async_fail + 1, 0, 4, meas_stream));
+        launch_psi6_retry(m, h1, hp, dre, dim, async_fail + 1, async_fail, meas_work, meas_stream);
+    } else {
+        launch_psi6(m, hp, dre, dim, async_fail, loc, meas_work, meas_stream);
+    }
     HIPCHK(hipGetLastError());
     if (field) {
         launch_psi6_field(m, dre, dim, dfr, dfi, meas_stream);

@@ -30,8 +30,9 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kNF = 24, kNH = 64, kNO = 20, kNPARAM = 7060;
-constexpr int kPW1 = 0, kPB1 = kPW1 + 64 * 24, kPW2 = kPB1 + 64, kPB2 = kPW2 + 64 * 64,
-              kPW3 = kPB2 + 64, kPB3 = kPW3 + 20 * 64;
+constexpr int kPW1 = 0, kPB1 = kPW1 + kNH * kNF, kPW2 = kPB1 + kNH, kPB2 = kPW2 + kNH * kNH,
+              kPW3 = kPB2 + kNH, kPB3 = kPW3 + kNO * kNH;
+static_assert(kPB3 + kNO == kNPARAM, "flat parameter vector: W1, b1, W2, b2, W3, b3");
 constexpr int kStreamTrain = 5;
 
 // BF16 weights in the layouts the GEMMs read (k contiguous), zero padded:

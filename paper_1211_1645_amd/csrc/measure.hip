@@ -423,9 +423,14 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, floa
     }
 }
 
+// gate: NULL, or a flag that a narrower pass set when its search fell short;
+// with the flag clear the launch does nothing and leaves that pass's psi_j
+// and partials in place.
 template <int H>
 __global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, float *im,
-                                                   uint32_t *fail, double2 *part) {
+                                                   uint32_t *fail, double2 *part,
+                                                   const uint32_t *gate) {
+    if (gate != nullptr && *gate == 0u) return;  // uniform over the grid
     __shared__ Stage S;
     __shared__ double2 wpart[4];
     const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
@@ -470,14 +475,36 @@ __global__ void __launch_bounds__(256) k_psi_reduce(const double2 *part, uint32_
     }
 }
 
+namespace {
+void launch_psi6_tile(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
+                      double2 *part, const uint32_t *gate, uint32_t G, hipStream_t st) {
+    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
+    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
+    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
+}
+uint32_t psi6_grid(const MeasureView &m) {
+    const uint32_t nb = (m.M + kPT - 1) / kPT;
+    return nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+}
+}  // namespace
+
 void launch_psi6_tiled(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
                        void *work, hipStream_t st) {
-    const uint32_t nb = (m.M + kPT - 1) / kPT;
-    const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
+    const uint32_t G = psi6_grid(m);
     double2 *part = static_cast<double2 *>(work);
-    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, fail, part);
-    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, fail, part);
-    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, fail, part);
+    launch_psi6_tile(m, h, re, im, fail, part, nullptr, G, st);
+    k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
+}
+
+// Stencil h1 first; a second pass with h2 > h1 runs only if the first one's
+// search fell short for some disk (flag short1, which the caller has
+// cleared), decided on the device.  fail receives the second pass's verdict.
+void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re, float *im,
+                       uint32_t *short1, uint32_t *fail, void *work, hipStream_t st) {
+    const uint32_t G = psi6_grid(m);
+    double2 *part = static_cast<double2 *>(work);
+    launch_psi6_tile(m, h1, re, im, short1, part, nullptr, G, st);
+    launch_psi6_tile(m, h2, re, im, fail, part, short1, G, st);
     k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
 }
 

@@ -85,7 +85,9 @@ struct Box {
     hipStream_t meas_stream = nullptr;
     hipEvent_t ev_swept = nullptr, ev_meas = nullptr;
     bool meas_pending = false;
-    uint32_t *async_fail = nullptr;  // OR of the neighbour-search failures since the last wait
+    // [0]: OR of the neighbour-search failures since the last wait (of the
+    // widest pass); [1]: the narrower first pass's flag of one measurement
+    uint32_t *async_fail = nullptr;
     int join_meas();                 // orders the box's stream after a pending measurement
     int measure_async(double *Psi_dev, bool field);
     uint64_t graph_key = 0;

@@ -78,6 +78,10 @@ void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, u
                          void *work, hipStream_t st);
 void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
                  const uint32_t *loc, void *work, hipStream_t st);
+// psi6 with stencil h1, then h2 on the device only where h1 fell short (tiled
+// kernels only; h1 < h2).
+void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re, float *im,
+                       uint32_t *short1, uint32_t *fail, void *work, hipStream_t st);
 void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
                        float *fim, hipStream_t st);
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);
