@@ -99,8 +99,10 @@ def stored_tau():
     d = json.load(open(path))
     keys = ("tau_efold_displacements_per_disk", "tau_displacements_per_disk",
             "paper_tau_displacements_per_disk", "decorrelations_per_s", "sweeps_per_s",
+            "tau_efold_mean_displacements_per_disk", "tau_efold_se_displacements_per_disk",
             "command")
     out = {k: d.get(k) for k in keys}
+    out["independent_runs"] = len(d.get("independent_runs", [])) or 1
     out["N"], out["eta"], out["source"] = 512 * 512, 0.698, "profiles/psi6_tau_512sq_eta0698.json"
     return out
 
