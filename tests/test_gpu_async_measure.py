@@ -48,3 +48,32 @@ def test_async_rejects_pressure_blocks(gpu_lib):
     b = gpu_lib.Box(4096, 0.7, seed=1, step_m=20, hist_block=10)
     with pytest.raises(gpu_lib.MPMCError):
         b.measure_async()
+
+
+def test_async_wider_search_runs_on_device(gpu_lib):
+    """At eta = 0.5 some disks have their sixth neighbour beyond the two cells
+    of the first psi_6 pass (checked here from the box's own positions), so
+    the device-gated second pass must run: the asynchronous Psi_6 still
+    equals the synchronous one bit for bit and no failure is reported."""
+    import torch
+    kw = dict(step_m=40, lattice="triangular")
+    a = gpu_lib.Box(4096, 0.5, seed=0, **kw)
+    s = gpu_lib.Box(4096, 0.5, seed=0, **kw)
+    a.sweep(200)
+    s.sweep(200)
+    info = a.info()
+    x, y = a.positions()
+    L, w = info["M"] * info["w"], info["w"]
+    d6 = np.empty(len(x))
+    for i in range(0, len(x), 512):
+        dx = x[i:i + 512, None] - x[None, :]
+        dx -= L * np.round(dx / L)
+        dy = y[i:i + 512, None] - y[None, :]
+        dy -= L * np.round(dy / L)
+        d6[i:i + 512] = np.sort(np.hypot(dx, dy), axis=1)[:, 6]
+    assert (d6 > 2 * w).any() and (d6 < 3 * w).all()
+    psi = torch.zeros(2, dtype=torch.float64, device="cuda")
+    a.measure_async(psi, field=True)
+    assert a.measure_wait() is False
+    _, _, P = s.psi6_field()
+    assert psi[0].item() == P.real and psi[1].item() == P.imag
