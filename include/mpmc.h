@@ -256,15 +256,16 @@ int mpmc_power_law(const double *x, const double *y, uint32_t n, double *exponen
 
 /* Asynchronous measurement of the current configuration: adds it to the
  * contact histogram (as mpmc_accumulate_contacts) and evaluates psi_6 (as
- * mpmc_psi6_field, with the widest staged stencil, 3 cells) on a
+ * mpmc_psi6_field: a 2-cell stencil, then the widest staged stencil, 3
+ * cells, where the first fell short, decided on the device) on a
  * stream of the box's own, so that the kernels overlap the sweeps that
  * follow; nothing is copied to the host.  Psi (may be NULL): device pointer
  * to two doubles that receive the global Psi_6 (re, im) once the kernels
  * have run; field != 0 also refreshes the psi field (mpmc_psi6_field's
  * buffers).  The next sweeps wait for the measurement only before their last
  * sweep overwrites the state it reads; every other call on the box waits for
- * it on the box's stream.  A neighbour search too short for some disk is
- * not retried: it sets a flag that mpmc_measure_wait reports.  MPMC_EINVAL
+ * it on the box's stream.  A neighbour search too short even with the
+ * widest stencil sets a flag that mpmc_measure_wait reports.  MPMC_EINVAL
  * with hist_block > 0 or where the staged kernels do not apply (cells of
  * more than 4 disks, M < 6); MPMC_ESTATE for a box of a batch. */
 int mpmc_measure_async(mpmc_box b, double *Psi, int field);
