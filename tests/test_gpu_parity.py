@@ -255,6 +255,22 @@ def test_full_size_parity_sampled(gpu_lib):
     assert g.validate() == (0, 0)
 
 
+@pytest.mark.parametrize("eta", [0.700, 0.720])
+def test_paper_scale_densities_bit_exact(gpu_lib, eta):
+    """N = 1024^2 at the ends of the paper's density scan (M = 1084 and 1068,
+    a multiple of none of the tile sides, so the last tiles are ragged):
+    cell lists after 2 sweeps bit for bit against the oracle."""
+    cfg = dict(N=1024 * 1024, eta=eta, seed=1, lattice=1, step_m=20)
+    g = gpu_box(gpu_lib, **cfg)
+    o = OracleBox(**cfg)
+    gi = g.info()
+    assert gi["M"] == o.info()["M"] and gi["tile"] > 0 and gi["M"] % gi["tile"] != 0
+    g.sweep(2)
+    o.sweep(2)
+    assert_same_state(g, o)
+    assert g.validate() == (0, 0)
+
+
 def test_gpu_n2_closed_form_pressure(gpu_lib):
     """Statistical pin of the GPU sampler itself: for N = 2 the separation is
     uniform outside the excluded disk, so P* = (4 eta/pi)(1-eta)/(1-2 eta)."""
