@@ -271,6 +271,18 @@ def test_paper_scale_densities_bit_exact(gpu_lib, eta):
     assert g.validate() == (0, 0)
 
 
+def test_largest_box_one_sweep_bit_exact(gpu_lib):
+    """N = 4096^2 (M = 4288, 18.4 M cells, the state far beyond the Infinity
+    Cache): cell lists and positions after one sweep bit for bit."""
+    cfg = dict(N=4096 * 4096, eta=0.716, seed=2, lattice=1, step_m=20)
+    g = gpu_box(gpu_lib, **cfg)
+    o = OracleBox(**cfg)
+    assert g.info()["M"] == 4288
+    g.sweep(1)
+    o.sweep(1)
+    assert_same_state(g, o)
+
+
 def test_gpu_n2_closed_form_pressure(gpu_lib):
     """Statistical pin of the GPU sampler itself: for N = 2 the separation is
     uniform outside the excluded disk, so P* = (4 eta/pi)(1-eta)/(1-2 eta)."""
