@@ -77,3 +77,16 @@ def test_async_wider_search_runs_on_device(gpu_lib):
     assert a.measure_wait() is False
     _, _, P = s.psi6_field()
     assert psi[0].item() == P.real and psi[1].item() == P.imag
+
+
+def test_async_reports_search_too_short(gpu_lib):
+    """At eta = 0.15, after the lattice has dissolved, the sixth neighbour of
+    most disks lies beyond three cells, the widest staged stencil: the
+    asynchronous measurement cannot retry further and must say so, once."""
+    b = gpu_lib.Box(4096, 0.15, seed=0, step_m=255, lattice="triangular")
+    b.sweep(300)
+    b.measure_async()
+    assert b.measure_wait() is True
+    assert b.measure_wait() is False
+    b.measure_async()
+    assert b.measure_wait() is True
