@@ -184,6 +184,32 @@ __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_
     return bad;
 }
 
+// One trial of slot `slot` of the cell whose records are (mx, my), with the
+// step (dxs, dys): the in-cell test, the overlap test and, if both pass, the
+// move.  SL = 2 when no cell of the region holds more than two disks, so the
+// slot is 0 or 1 and only the first two components are read and written.
+template <int SL, int H, int CX, int CY, typename LdsT>
+__device__ __forceinline__ bool try_move(const LdsT &L, int base_ax, uint32_t slot, float4 &mx,
+                                         float4 &my, float dxs, float dys, float lo_b, float hi_b,
+                                         float w) {
+    const float ox = SL > 2 ? pick4(mx, slot) : ((slot & 1u) ? mx.y : mx.x);
+    const float oy = SL > 2 ? pick4(my, slot) : ((slot & 1u) ? my.y : my.x);
+    const float xn = ox + dxs, yn = oy + dys;
+    const bool inside = xn >= lo_b && xn < hi_b && yn >= lo_b && yn < hi_b;
+    const bool acc = inside && !overlaps_any<SL, H, CX, CY>(L, base_ax, slot, mx, my, xn, yn, w);
+    if (SL > 2) {
+        mx = acc ? put4(mx, slot, xn) : mx;
+        my = acc ? put4(my, slot, yn) : my;
+    } else {
+        const bool a0 = acc && slot == 0u, a1 = acc && slot == 1u;
+        mx.x = a0 ? xn : mx.x;
+        mx.y = a1 ? xn : mx.y;
+        my.x = a0 ? yn : my.x;
+        my.y = a1 ? yn : my.y;
+    }
+    return acc;
+}
+
 // One colour sub-sweep over the LDS region: pass p updates the cells of
 // colour (CX, CY) with region coordinates in [p + 1, RL - p - 1), one lane per
 // cell of that rectangle of the colour plane; lanes of empty cells idle.
@@ -230,15 +256,12 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
             const Words w4 = draw(v.seed_lo, v.seed_hi, ctx.sweep, cell, t, kStreamTrial);
             const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n)
                                                    : (perm >> (4 * (t % n))) & 0xFu;
-            const float xn = pick4(mx, slot) + step_from_word(w4.w1, v.step_m);
-            const float yn = pick4(my, slot) + step_from_word(w4.w2, v.step_m);
+            const float dxs = step_from_word(w4.w1, v.step_m);
+            const float dys = step_from_word(w4.w2, v.step_m);
             if (own) ++trials;
-            const bool inside = xn >= lo_b && xn < hi_b && yn >= lo_b && yn < hi_b;
-            const bool bad = ctx.big ? overlaps_any<4, H, CX, CY>(L, base_ax, slot, mx, my, xn, yn, w)
-                                     : overlaps_any<2, H, CX, CY>(L, base_ax, slot, mx, my, xn, yn, w);
-            const bool acc = inside && !bad;
-            mx = acc ? put4(mx, slot, xn) : mx;
-            my = acc ? put4(my, slot, yn) : my;
+            const bool acc =
+                ctx.big ? try_move<4, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w)
+                        : try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
             if (own && acc) ++accepts;
         }
         L.x[e] = mx;
