@@ -25,6 +25,8 @@
 // runs without branches.  Cells are stored by colour plane so that the
 // lanes of a wave, which work on cells of one colour, read consecutive
 // records.
+#include <type_traits>
+
 #include "mpmc_kernels.hpp"
 
 namespace mpmc {
@@ -389,102 +391,109 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     // (ex - wx, ey - wy) of the next sweep's grid, shifted by s'.
     const SweepDraws dn = sweep_draws(v.seed_lo, v.seed_hi, sweep + 1, v.W);
     const float sxn = (float)dn.kx * kQ, syn = (float)dn.ky * kQ;
-    float4 ux_r[NEIT], uy_r[NEIT];
-    uint32_t me_r[NEIT];
+    // Only the slots in use are read: two when no region cell holds more
+    // (the counts do not change during the passes), else four.
+    auto rebin = [&](auto slots) {
+        constexpr int SL = decltype(slots)::value;
+        float4 ux_r[NEIT], uy_r[NEIT];
+        uint32_t me_r[NEIT];
 #pragma unroll
-    for (int i = 0; i < NEIT; ++i) {
-        const int f = tid + i * THREADS;
-        const int ex = f % TE, ey = f / TE;
-        const bool in_ext = f < NE && ex <= own_x && ey <= own_y;
-        const int li = pidx<R>(ex + kHalo, ey + kHalo);
-        const uint32_t m = in_ext ? L.cnt[li] : 0u;
-        const float4 sx4 = L.x[in_ext ? li : 0], sy4 = L.y[in_ext ? li : 0];
-        float4 ux, uy;
-        ux.x = sx4.x + cen;
-        ux.y = sx4.y + cen;
-        ux.z = sx4.z + cen;
-        ux.w = sx4.w + cen;
-        uy.x = sy4.x + cen;
-        uy.y = sy4.y + cen;
-        uy.z = sy4.z + cen;
-        uy.w = sy4.w + cen;
-        me_r[i] = m;
-        ux_r[i] = ux;
-        uy_r[i] = uy;
-        if (in_ext && ex < own_x && ey < own_y && v.cnt_can) {
-            const uint32_t c = (I0 + ex) + __umul24(M, J0 + ey);
-            el(v.cnt_can, c) = (uint8_t)m;
+        for (int i = 0; i < NEIT; ++i) {
+            const int f = tid + i * THREADS;
+            const int ex = f % TE, ey = f / TE;
+            const bool in_ext = f < NE && ex <= own_x && ey <= own_y;
+            const int li = pidx<R>(ex + kHalo, ey + kHalo);
+            const uint32_t m = in_ext ? L.cnt[li] : 0u;
+            const float4 sx4 = L.x[in_ext ? li : 0], sy4 = L.y[in_ext ? li : 0];
+            float4 ux, uy;
+            ux.x = sx4.x + cen;
+            ux.y = sx4.y + cen;
+            uy.x = sy4.x + cen;
+            uy.y = sy4.y + cen;
+            ux.z = SL > 2 ? sx4.z + cen : 0.0f;
+            ux.w = SL > 2 ? sx4.w + cen : 0.0f;
+            uy.z = SL > 2 ? sy4.z + cen : 0.0f;
+            uy.w = SL > 2 ? sy4.w + cen : 0.0f;
+            me_r[i] = m;
+            ux_r[i] = ux;
+            uy_r[i] = uy;
+            if (in_ext && ex < own_x && ey < own_y && v.cnt_can) {
+                const uint32_t c = (I0 + ex) + __umul24(M, J0 + ey);
+                el(v.cnt_can, c) = (uint8_t)m;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                if ((uint32_t)s < m) {
-                    el(v.x_can, s * NC + c) = comp4(ux, s);
-                    el(v.y_can, s * NC + c) = comp4(uy, s);
-                    el(v.tag_can, s * NC + c) = s == 0 ? tg_r[i].x : s == 1 ? tg_r[i].y
-                                          : s == 2 ? tg_r[i].z : tg_r[i].w;
+                for (int s = 0; s < SL; ++s) {
+                    if ((uint32_t)s < m) {
+                        el(v.x_can, s * NC + c) = comp4(ux, s);
+                        el(v.y_can, s * NC + c) = comp4(uy, s);
+                        el(v.tag_can, s * NC + c) = s == 0 ? tg_r[i].x : s == 1 ? tg_r[i].y
+                                              : s == 2 ? tg_r[i].z : tg_r[i].w;
+                    }
                 }
             }
-        }
-        uint32_t g = 0;
+            uint32_t g = 0;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint32_t cls = (uint32_t)(comp4(ux, s) < sxn) | ((uint32_t)(comp4(uy, s) < syn) << 1);
-            g += ((uint32_t)s < m) ? (1u << (3 * cls)) : 0u;
+            for (int s = 0; s < SL; ++s) {
+                const uint32_t cls = (uint32_t)(comp4(ux, s) < sxn) | ((uint32_t)(comp4(uy, s) < syn) << 1);
+                g += ((uint32_t)s < m) ? (1u << (3 * cls)) : 0u;
+            }
+            if (f < NE) L.gcnt[f] = (uint16_t)g;
         }
-        if (f < NE) L.gcnt[f] = (uint16_t)g;
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // ---- scatter into the next sweep's cell lists ---------------------------
-    // New cell (I, J) takes the disks of old (I, J) that do not wrap, then
-    // those of (I+1, J) wrapping in x only, (I, J+1) in y only, (I+1, J+1) in
-    // both, each in old slot order.  A disk's slot follows from the class
-    // counts of the old cells before its own in that order.
+        // ---- scatter into the next sweep's cell lists ---------------------------
+        // New cell (I, J) takes the disks of old (I, J) that do not wrap, then
+        // those of (I+1, J) wrapping in x only, (I, J+1) in y only, (I+1, J+1) in
+        // both, each in old slot order.  A disk's slot follows from the class
+        // counts of the old cells before its own in that order.
 #pragma unroll
-    for (int i = 0; i < NEIT; ++i) {
-        const int f = tid + i * THREADS;
-        const int ex = f % TE, ey = f / TE;
-        if (f >= NE || ex > own_x || ey > own_y) continue;
-        const uint32_t m = me_r[i];
-        const float4 ux = ux_r[i], uy = uy_r[i];
-        const uint4 tg = tg_r[i];
-        const int exm = ex > 0 ? ex - 1 : 0, eym = ey > 0 ? ey - 1 : 0;
-        const int exp1 = ex < TE - 1 ? ex + 1 : TE - 1;
-        const uint32_t g_l = L.gcnt[exm + TE * ey];     // (ex-1, ey)
-        const uint32_t g_d = L.gcnt[ex + TE * eym];     // (ex, ey-1)
-        const uint32_t g_dr = L.gcnt[exp1 + TE * eym];  // (ex+1, ey-1)
-        const uint32_t g_dl = L.gcnt[exm + TE * eym];   // (ex-1, ey-1)
-        // base slot of each class in its destination, 8 bits per class
-        const uint32_t b1 = g_l & 7u;
-        const uint32_t b2 = (g_d & 7u) + ((g_dr >> 3) & 7u);
-        const uint32_t b3 = (g_dl & 7u) + ((g_d >> 3) & 7u) + ((g_l >> 6) & 7u);
-        const uint32_t bases = (b1 << 8) | (b2 << 16) | (b3 << 24);
-        uint32_t seen = 0;  // 3-bit counters per class within this old cell
-        const uint32_t nc0 = (I0 + ex) + __umul24(M, J0 + ey);  // new cell (ex, ey)
+        for (int i = 0; i < NEIT; ++i) {
+            const int f = tid + i * THREADS;
+            const int ex = f % TE, ey = f / TE;
+            if (f >= NE || ex > own_x || ey > own_y) continue;
+            const uint32_t m = me_r[i];
+            const float4 ux = ux_r[i], uy = uy_r[i];
+            const uint4 tg = tg_r[i];
+            const int exm = ex > 0 ? ex - 1 : 0, eym = ey > 0 ? ey - 1 : 0;
+            const int exp1 = ex < TE - 1 ? ex + 1 : TE - 1;
+            const uint32_t g_l = L.gcnt[exm + TE * ey];     // (ex-1, ey)
+            const uint32_t g_d = L.gcnt[ex + TE * eym];     // (ex, ey-1)
+            const uint32_t g_dr = L.gcnt[exp1 + TE * eym];  // (ex+1, ey-1)
+            const uint32_t g_dl = L.gcnt[exm + TE * eym];   // (ex-1, ey-1)
+            // base slot of each class in its destination, 8 bits per class
+            const uint32_t b1 = g_l & 7u;
+            const uint32_t b2 = (g_d & 7u) + ((g_dr >> 3) & 7u);
+            const uint32_t b3 = (g_dl & 7u) + ((g_d >> 3) & 7u) + ((g_l >> 6) & 7u);
+            const uint32_t bases = (b1 << 8) | (b2 << 16) | (b3 << 24);
+            uint32_t seen = 0;  // 3-bit counters per class within this old cell
+            const uint32_t nc0 = (I0 + ex) + __umul24(M, J0 + ey);  // new cell (ex, ey)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if ((uint32_t)s >= m) break;
-            const float us = comp4(ux, s), vs = comp4(uy, s);
-            const uint32_t wx = us < sxn, wy = vs < syn, cls = wx | (wy << 1);
-            const uint32_t slot = ((bases >> (8 * cls)) & 0xFFu) + ((seen >> (3 * cls)) & 7u);
-            seen += 1u << (3 * cls);
-            const int nx = ex - (int)wx, ny = ey - (int)wy;
-            if (nx < 0 || nx >= own_x || ny < 0 || ny >= own_y || slot >= 4) continue;
-            const uint32_t at = nc0 - wx - (wy ? M : 0u) + slot * NC;
-            el(v.x_out, at) = (us - sxn) + (wx ? w : 0.0f);
-            el(v.y_out, at) = (vs - syn) + (wy ? w : 0.0f);
-            el(v.tag_out, at) = s == 0 ? tg.x : s == 1 ? tg.y : s == 2 ? tg.z : tg.w;
+            for (int s = 0; s < SL; ++s) {
+                if ((uint32_t)s >= m) break;
+                const float us = comp4(ux, s), vs = comp4(uy, s);
+                const uint32_t wx = us < sxn, wy = vs < syn, cls = wx | (wy << 1);
+                const uint32_t slot = ((bases >> (8 * cls)) & 0xFFu) + ((seen >> (3 * cls)) & 7u);
+                seen += 1u << (3 * cls);
+                const int nx = ex - (int)wx, ny = ey - (int)wy;
+                if (nx < 0 || nx >= own_x || ny < 0 || ny >= own_y || slot >= 4) continue;
+                const uint32_t at = nc0 - wx - (wy ? M : 0u) + slot * NC;
+                el(v.x_out, at) = (us - sxn) + (wx ? w : 0.0f);
+                el(v.y_out, at) = (vs - syn) + (wy ? w : 0.0f);
+                el(v.tag_out, at) = s == 0 ? tg.x : s == 1 ? tg.y : s == 2 ? tg.z : tg.w;
+            }
+            if (ex < own_x && ey < own_y) {  // the count of new cell (ex, ey)
+                const uint32_t g_me = L.gcnt[f];
+                const uint32_t g_r = L.gcnt[ex + 1 + TE * ey];         // (ex+1, ey)
+                const uint32_t g_u = L.gcnt[ex + TE * (ey + 1)];       // (ex, ey+1)
+                const uint32_t g_ur = L.gcnt[ex + 1 + TE * (ey + 1)];  // (ex+1, ey+1)
+                const uint32_t n = (g_me & 7u) + ((g_r >> 3) & 7u) + ((g_u >> 6) & 7u) +
+                                   ((g_ur >> 9) & 7u);
+                if (n > 4) atomicOr((uint32_t *)&v.dev->overflow, 1u);
+                el(v.cnt_out, nc0) = (uint8_t)(n > 4 ? 4 : n);
+            }
         }
-        if (ex < own_x && ey < own_y) {  // the count of new cell (ex, ey)
-            const uint32_t g_me = L.gcnt[f];
-            const uint32_t g_r = L.gcnt[ex + 1 + TE * ey];         // (ex+1, ey)
-            const uint32_t g_u = L.gcnt[ex + TE * (ey + 1)];       // (ex, ey+1)
-            const uint32_t g_ur = L.gcnt[ex + 1 + TE * (ey + 1)];  // (ex+1, ey+1)
-            const uint32_t n = (g_me & 7u) + ((g_r >> 3) & 7u) + ((g_u >> 6) & 7u) +
-                               ((g_ur >> 9) & 7u);
-            if (n > 4) atomicOr((uint32_t *)&v.dev->overflow, 1u);
-            el(v.cnt_out, nc0) = (uint8_t)(n > 4 ? 4 : n);
-        }
-    }
+    };
+    if (ctx.big) rebin(std::integral_constant<int, 4>{});
+    else rebin(std::integral_constant<int, 2>{});
     count_trials((DevScalars *)v.dev, trials, accepts);
 }
 
