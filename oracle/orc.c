@@ -305,26 +305,58 @@ static int overlaps(float dx, float dy) {
     return r2 < 4.0f;
 }
 
-static void trial_cell(orc_box *b, uint32_t ci, uint32_t cj) {
+/* The shuffled order of a cell's slots for several trials (Sec. II.B):
+ * Fisher-Yates, for i = n-1 down to 1 swap slot i with slot
+ * floor(word * (i+1) / 2^32); word e = n-1-i of stream 1, call index e / 4
+ * in the trial field. */
+static void shuffle_slots(const orc_box *b, uint32_t cell, uint32_t n, uint32_t perm[8]) {
+    for (uint32_t s = 0; s < n; ++s) perm[s] = s;
+    uint32_t wds[4];
+    uint32_t have = 0xFFFFFFFFu;
+    for (uint32_t i = n - 1; i >= 1; --i) {
+        uint32_t e = n - 1 - i;
+        if (e / 4 != have) { draw(b, b->sweep, cell, e / 4, 1, wds); have = e / 4; }
+        uint32_t j = mulhi(wds[e % 4], i + 1);
+        uint32_t tmp = perm[i]; perm[i] = perm[j]; perm[j] = tmp;
+    }
+}
+
+/* Accepted moves recorded by the collecting sweep: features at the old
+ * position and the displacement. */
+typedef struct {
+    float *F, *D;
+    uint64_t cap, n;
+} recorder;
+
+/* Any other disk of the 3 x 3 block overlapping the disk of slot `slot` of
+ * cell (ci, cj) placed at cell-local (xn, yn) (Sec. II.A, Sec. II.B: the
+ * neighbour cells hold every disk within reach since w >= 2). */
+static int overlaps_block(const orc_box *b, uint32_t ci, uint32_t cj, uint32_t slot, float xn,
+                          float yn) {
+    uint32_t M = b->M, cell = ci + M * cj;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+            uint32_t nb = ((ci + M + di) % M) + M * ((cj + M + dj) % M);
+            float cwx = (float)di * b->w, cwy = (float)dj * b->w;
+            for (uint32_t s = 0; s < b->cnt[nb]; ++s) {
+                if (nb == cell && s == slot) continue;
+                uint32_t kk = nb * b->cap + s;
+                float ddx = (b->x[kk] - xn) + cwx;
+                float ddy = (b->y[kk] - yn) + cwy;
+                if (overlaps(ddx, ddy)) return 1;
+            }
+        }
+    return 0;
+}
+
+static void trial_cell(orc_box *b, uint32_t ci, uint32_t cj, void *ctx) {
+    recorder *rec = (recorder *)ctx;
     uint32_t M = b->M, cap = b->cap;
     uint32_t cell = ci + M * cj;
     uint32_t n = b->cnt[cell];
     if (n == 0) return;
     uint32_t perm[8];
-    if (b->n_trial > 1) {
-        /* Fisher-Yates over the slots: for i = n-1 down to 1, swap slot i with
-         * slot floor(word * (i+1) / 2^32); word e = n-1-i of stream 1, call
-         * index e / 4 in the trial field. */
-        for (uint32_t s = 0; s < n; ++s) perm[s] = s;
-        uint32_t wds[4];
-        uint32_t have = 0xFFFFFFFFu;
-        for (uint32_t i = n - 1; i >= 1; --i) {
-            uint32_t e = n - 1 - i;
-            if (e / 4 != have) { draw(b, b->sweep, cell, e / 4, 1, wds); have = e / 4; }
-            uint32_t j = mulhi(wds[e % 4], i + 1);
-            uint32_t tmp = perm[i]; perm[i] = perm[j]; perm[j] = tmp;
-        }
-    }
+    if (b->n_trial > 1) shuffle_slots(b, cell, n, perm);
     for (uint32_t t = 0; t < b->n_trial; ++t) {
         uint32_t w4[4];
         draw(b, b->sweep, cell, t, 0, w4);
@@ -337,20 +369,15 @@ static void trial_cell(orc_box *b, uint32_t ci, uint32_t cj) {
         float xn = b->x[k] + dx, yn = b->y[k] + dy;  /* exact */
         b->trials++;
         if (!(xn >= 0.0f && xn < b->w && yn >= 0.0f && yn < b->w)) continue;
-        int bad = 0;
-        for (int dj = -1; dj <= 1 && !bad; ++dj)
-            for (int di = -1; di <= 1 && !bad; ++di) {
-                uint32_t nb = ((ci + M + di) % M) + M * ((cj + M + dj) % M);
-                float cwx = (float)di * b->w, cwy = (float)dj * b->w;
-                for (uint32_t s = 0; s < b->cnt[nb]; ++s) {
-                    if (nb == cell && s == slot) continue;
-                    uint32_t kk = nb * cap + s;
-                    float ddx = (b->x[kk] - xn) + cwx;
-                    float ddy = (b->y[kk] - yn) + cwy;
-                    if (overlaps(ddx, ddy)) { bad = 1; break; }
-                }
+        if (overlaps_block(b, ci, cj, slot, xn, yn)) continue;
+        if (rec) {
+            if (rec->n < rec->cap) {
+                orc_features(b, cell, b->tag[k], b->x[k], b->y[k], rec->F + rec->n * 24);
+                rec->D[2 * rec->n] = dx;
+                rec->D[2 * rec->n + 1] = dy;
             }
-        if (bad) continue;
+            rec->n++;
+        }
         b->x[k] = xn;
         b->y[k] = yn;
         b->accepts++;
@@ -370,7 +397,11 @@ static void colour_order(uint32_t p, int order[4]) {
     order[3] = avail[0];
 }
 
-void orc_sweep(orc_box *b, uint64_t k, int cell_order) {
+typedef void (*cell_fn)(orc_box *b, uint32_t ci, uint32_t cj, void *ctx);
+
+/* k sweeps, each cell of a colour running `trials` (the plain trial, the
+ * learned trial or the recording plain trial). */
+static void sweeps_with(orc_box *b, uint64_t k, int cell_order, cell_fn trials, void *ctx) {
     uint32_t M = b->M;
     for (uint64_t it = 0; it < k; ++it) {
         uint32_t g[4];
@@ -390,11 +421,21 @@ void orc_sweep(orc_box *b, uint64_t k, int cell_order) {
                     uint32_t ci, cj;
                     if (cell_order == 2) { ci = 2 * ai + cx; cj = 2 * bi + cy; }
                     else { ci = 2 * bi + cx; cj = 2 * ai + cy; }
-                    trial_cell(b, ci, cj);
+                    trials(b, ci, cj, ctx);
                 }
         }
         b->sweep++;
     }
+}
+
+void orc_sweep(orc_box *b, uint64_t k, int cell_order) {
+    sweeps_with(b, k, cell_order, trial_cell, NULL);
+}
+
+uint64_t orc_sweep_collect(orc_box *b, uint64_t k, float *F, float *D, uint64_t cap) {
+    recorder rec = {F, D, cap, 0};
+    sweeps_with(b, k, 0, trial_cell, &rec);
+    return rec.n;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -823,8 +864,11 @@ void orc_mlp_forward(const double *p, const double *f, double *out) {
 }
 
 /* Component k of the network output: (logit, mu_x, mu_y, a_x, a_y) at
- * out[5k..5k+4]; sigma = exp(a) with a clamped to [-7, 1]. */
-static double clampa(double a) { return a < -7.0 ? -7.0 : (a > 1.0 ? 1.0 : a); }
+ * out[5k..5k+4]; sigma = exp(a) with a clamped to [A_MIN, A_MAX]: widths
+ * from about 190 q to e sigma. */
+#define A_MIN (-10.0)
+#define A_MAX 1.0
+static double clampa(double a) { return a < A_MIN ? A_MIN : (a > A_MAX ? A_MAX : a); }
 
 double orc_gmm_logpdf(const double *out, double dx, double dy) {
     double lmax = -INFINITY, l[4], lw[4];
@@ -881,8 +925,8 @@ double orc_nll_grad(const double *p, const double *F, const double *D, uint32_t 
             dout[5 * k] = pi_[k] - r[k];
             dout[5 * k + 1] = -r[k] * ux[k] * exp(-ax[k]);
             dout[5 * k + 2] = -r[k] * uy[k] * exp(-ay[k]);
-            double inx = out[5 * k + 3] > -7.0 && out[5 * k + 3] < 1.0;
-            double iny = out[5 * k + 4] > -7.0 && out[5 * k + 4] < 1.0;
+            double inx = out[5 * k + 3] > A_MIN && out[5 * k + 3] < A_MAX;
+            double iny = out[5 * k + 4] > A_MIN && out[5 * k + 4] < A_MAX;
             dout[5 * k + 3] = -r[k] * (ux[k] * ux[k] - 1.0) * inx;
             dout[5 * k + 4] = -r[k] * (uy[k] * uy[k] - 1.0) * iny;
         }
@@ -922,4 +966,225 @@ void orc_adam(double *p, double *m, double *v, const double *g, uint32_t n, doub
         v[e] = b2 * v[e] + (1.0 - b2) * g[e] * g[e];
         p[e] -= lr * (m[e] / c1) / (sqrt(v[e] / c2) + eps);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal: an extension of the uniform trial move of Sec. II.B (the
+ * paper has no learned proposal).  A network maps the moving disk's
+ * neighbourhood f(x) to 20 numbers, read as a four-component Gaussian
+ * mixture, and the trial displacement D (delta = D q, D integer per axis)
+ * is drawn from the law on the q lattice
+ *
+ *   P(D | out) = e U(D) + (1 - e) G(D | out),
+ *
+ *   e     = E / 2^32, E the nearest integer to eps * 2^32 (the branch test
+ *           compares a 32-bit word with E, so e is exactly the branch
+ *           probability);
+ *   U(D)  = the plain trial's step: per axis D = m j, j odd, |j| <= 2^14 - 1,
+ *           each of the 2^14 values with probability 2^-14;
+ *   G(D)  = sum_k pi_k g_k(Dx; mu_xk, s_xk) g_k(Dy; mu_yk, s_yk): a component
+ *           k is chosen with probability pi_k (softmax of the logits), a
+ *           point is drawn from N(mu_k, diag(s_k^2)) (s = exp(clamp(a))) in
+ *           double precision and rounded to the nearest lattice point; draws
+ *           with |D| > 2^22 - 1 on either axis fail (the trial is rejected).
+ *           g(D; mu, s) is the Gaussian mass of the lattice cell
+ *           [D - 1/2, D + 1/2] q, written through the even Taylor terms of
+ *           the cell integral: (q/s) phi(u) (1 + h^2 He2(u) / 6 +
+ *           h^4 He4(u) / 120) with u = (D q - mu) / s, h = q / (2 s),
+ *           He2 = u^2 - 1, He4 = u^4 - 6 u^2 + 3; the next term, h^6 He6 / 5040,
+ *           is below 2e-14 relative for s >= e^-10 and |u| <= 9.
+ *
+ * Random words of trial t in cell c of sweep k (counter layout as above):
+ *   A = stream 0: A0 selects the disk and A1, A2 give the uniform step,
+ *       exactly as in the plain trial; A3 < E chooses U;
+ *   B = stream 2: (B0, B1) the component uniform, (B2, B3) the acceptance
+ *       uniform;
+ *   C = stream 4: (C0, C1) u1 in (0, 1], (C2, C3) u2 in [0, 1); the normal
+ *       pair is sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) (Box-Muller).
+ *   A 53-bit uniform from (hi, lo) is ((hi << 21) | (lo >> 11)) 2^-53.
+ *
+ * The trial is the Metropolis-Hastings step (extending Sec. II.B's local
+ * move): propose x' = x + D q; reject if the draw failed, x' leaves the cell
+ * or overlaps a disk; else accept when
+ * ln u_a < ln P(-D | out(x')) - ln P(D | out(x)).  With e = 1 it is the
+ * plain trial, word for word. */
+
+#define NBRANCH_SHIFT 32
+typedef struct {
+    double lp[4], mx[4], my[4], ax[4], ay[4];
+} mixture;
+
+static void mixture_of(const double *out, mixture *g) {
+    double lmax = -INFINITY;
+    for (int k = 0; k < 4; ++k) lmax = out[5 * k] > lmax ? out[5 * k] : lmax;
+    double z = 0.0;
+    for (int k = 0; k < 4; ++k) z += exp(out[5 * k] - lmax);
+    double lz = lmax + log(z);
+    for (int k = 0; k < 4; ++k) {
+        g->lp[k] = out[5 * k] - lz;
+        g->mx[k] = out[5 * k + 1];
+        g->my[k] = out[5 * k + 2];
+        g->ax[k] = clampa(out[5 * k + 3]);
+        g->ay[k] = clampa(out[5 * k + 4]);
+    }
+}
+
+static uint64_t branch_threshold(float eps) {
+    return (uint64_t)llrint((double)eps * 4294967296.0);
+}
+
+static double u53(uint32_t hi, uint32_t lo) {
+    return ldexp((double)(((uint64_t)hi << 21) | (lo >> 11)), -53);
+}
+
+static int on_step_lattice(int64_t D, uint32_t m) {
+    if (D % (int64_t)m != 0) return 0;
+    int64_t j = D / (int64_t)m;
+    return (j & 1) != 0 && llabs(j) <= 16383;
+}
+
+/* ln of the Gaussian mass of lattice cell D on one axis. */
+static double log_cell_mass(int64_t D, double mu, double a) {
+    double is = exp(-a);
+    double u = ((double)D * QD - mu) * is;
+    double h = 0.5 * QD * is;
+    double u2 = u * u, h2 = h * h;
+    double he2 = u2 - 1.0, he4 = (u2 - 6.0) * u2 + 3.0;
+    double corr = h2 * he2 / 6.0 + (h2 * h2) * he4 / 120.0;
+    return log(QD) - a - 0.5 * log(2.0 * M_PI) - 0.5 * u2 + log1p(corr);
+}
+
+static double log_add(double a, double b) {
+    double m = a > b ? a : b;
+    if (m == -INFINITY) return m;
+    return m + log1p(exp(-fabs(a - b)));
+}
+
+static double log_p(const mixture *g, int64_t Dx, int64_t Dy, uint32_t m, uint64_t E) {
+    double e = ldexp((double)E, -NBRANCH_SHIFT);
+    double lu = (on_step_lattice(Dx, m) && on_step_lattice(Dy, m)) ? -28.0 * M_LN2 : -INFINITY;
+    double lg = -INFINITY;
+    if (llabs(Dx) <= 4194303 && llabs(Dy) <= 4194303) {
+        double l[4], best = -INFINITY;
+        for (int k = 0; k < 4; ++k) {
+            l[k] = g->lp[k] + log_cell_mass(Dx, g->mx[k], g->ax[k]) +
+                   log_cell_mass(Dy, g->my[k], g->ay[k]);
+            best = l[k] > best ? l[k] : best;
+        }
+        if (best > -INFINITY) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += exp(l[k] - best);
+            lg = best + log(s);
+        }
+    }
+    return log_add(log(e) + lu, log1p(-e) + lg);
+}
+
+/* Draws D from P(. | g) with the words A, B, C; returns 0 for a failed draw. */
+static int learned_draw(const mixture *g, const uint32_t A[4], const uint32_t B[4],
+                        const uint32_t C[4], uint32_t m, uint64_t E, int64_t *Dx, int64_t *Dy) {
+    if ((uint64_t)A[3] < E) {
+        *Dx = (int64_t)m * (2 * (int64_t)(A[1] >> 18) + 1 - 16384);
+        *Dy = (int64_t)m * (2 * (int64_t)(A[2] >> 18) + 1 - 16384);
+        return 1;
+    }
+    double uc = u53(B[0], B[1]);
+    int k = 3;
+    double cum = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        cum += exp(g->lp[c]);
+        if (uc < cum) { k = c; break; }
+    }
+    double u1 = ldexp((double)((((uint64_t)C[0] << 21) | (C[1] >> 11)) + 1), -53);
+    double u2 = u53(C[2], C[3]);
+    double r = sqrt(-2.0 * log(u1));
+    double th = 2.0 * M_PI * u2;
+    double tx = (g->mx[k] + (exp(g->ax[k]) * r) * cos(th)) * 4194304.0;
+    double ty = (g->my[k] + (exp(g->ay[k]) * r) * sin(th)) * 4194304.0;
+    if (!(fabs(tx) < 4194303.5 && fabs(ty) < 4194303.5)) return 0;
+    *Dx = (int64_t)rint(tx);
+    *Dy = (int64_t)rint(ty);
+    return 1;
+}
+
+double orc_learned_logp(const double *out, int64_t Dx, int64_t Dy, uint32_t step_m, float eps) {
+    mixture g;
+    mixture_of(out, &g);
+    return log_p(&g, Dx, Dy, step_m, branch_threshold(eps));
+}
+
+void orc_learned_proposals(const double *out, uint32_t step_m, float eps, uint64_t seed,
+                           uint32_t n, int64_t *D, uint8_t *drawn, double *logp) {
+    mixture g;
+    mixture_of(out, &g);
+    uint64_t E = branch_threshold(eps);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t A[4], B[4], Cw[4];
+        uint32_t ca[4] = {0, i, 0, 0}, cb[4] = {0, i, 0, 2}, cc[4] = {0, i, 0, 4};
+        orc_philox((uint32_t)seed, (uint32_t)(seed >> 32), ca, A);
+        orc_philox((uint32_t)seed, (uint32_t)(seed >> 32), cb, B);
+        orc_philox((uint32_t)seed, (uint32_t)(seed >> 32), cc, Cw);
+        int64_t Dx = 0, Dy = 0;
+        int ok = learned_draw(&g, A, B, Cw, step_m, E, &Dx, &Dy);
+        D[2 * i] = Dx;
+        D[2 * i + 1] = Dy;
+        if (drawn) drawn[i] = (uint8_t)ok;
+        if (logp) logp[i] = ok ? log_p(&g, Dx, Dy, step_m, E) : NAN;
+    }
+}
+
+typedef struct {
+    const double *params;
+    uint64_t E;
+} learned_ctx;
+
+/* The network's mixture for the disk of tag `self` at cell-local (x, y) of
+ * `cell`, all other disks where they are. */
+static void mixture_at(const orc_box *b, const double *params, uint32_t cell, uint32_t self,
+                       float x, float y, mixture *g) {
+    float f32[24];
+    double f[24], out[20];
+    orc_features(b, cell, self, x, y, f32);
+    for (int e = 0; e < 24; ++e) f[e] = (double)f32[e];
+    orc_mlp_forward(params, f, out);
+    mixture_of(out, g);
+}
+
+static void trial_cell_learned(orc_box *b, uint32_t ci, uint32_t cj, void *ctx) {
+    const learned_ctx *L = (const learned_ctx *)ctx;
+    uint32_t M = b->M, cap = b->cap;
+    uint32_t cell = ci + M * cj;
+    uint32_t n = b->cnt[cell];
+    if (n == 0) return;
+    uint32_t perm[8];
+    if (b->n_trial > 1) shuffle_slots(b, cell, n, perm);
+    for (uint32_t t = 0; t < b->n_trial; ++t) {
+        uint32_t A[4], B[4], Cw[4];
+        draw(b, b->sweep, cell, t, 0, A);
+        draw(b, b->sweep, cell, t, 2, B);
+        draw(b, b->sweep, cell, t, 4, Cw);
+        uint32_t slot = (b->n_trial == 1) ? mulhi(A[0], n) : perm[t % n];
+        uint32_t k = cell * cap + slot, self = b->tag[k];
+        b->trials++;
+        mixture g, gr;
+        mixture_at(b, L->params, cell, self, b->x[k], b->y[k], &g);
+        int64_t Dx, Dy;
+        if (!learned_draw(&g, A, B, Cw, b->step_m, L->E, &Dx, &Dy)) continue;
+        int64_t U = (int64_t)ldexp((double)b->x[k], Q_SHIFT) + Dx;
+        int64_t V = (int64_t)ldexp((double)b->y[k], Q_SHIFT) + Dy;
+        if (U < 0 || U >= b->W || V < 0 || V >= b->W) continue;
+        float xn = (float)((double)U * QD), yn = (float)((double)V * QD);  /* exact */
+        if (overlaps_block(b, ci, cj, slot, xn, yn)) continue;
+        mixture_at(b, L->params, cell, self, xn, yn, &gr);
+        double d = log_p(&gr, -Dx, -Dy, b->step_m, L->E) - log_p(&g, Dx, Dy, b->step_m, L->E);
+        if (!(d >= 0.0) && !(log(u53(B[2], B[3])) < d)) continue;
+        b->x[k] = xn;
+        b->y[k] = yn;
+        b->accepts++;
+    }
+}
+
+void orc_sweep_learned(orc_box *b, const double *params, float eps, uint64_t k) {
+    learned_ctx L = {params, branch_threshold(eps)};
+    sweeps_with(b, k, 0, trial_cell_learned, &L);
 }

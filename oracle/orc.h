@@ -140,6 +140,24 @@ double orc_nll_grad(const double *p, const double *F, const double *D, uint32_t 
 void orc_adam(double *p, double *m, double *v, const double *g, uint32_t n, double lr,
               uint32_t t);
 
+/* The learned proposal as a law on the q lattice (the definition is written
+ * out above orc_learned_logp in orc.c): ln P(D | out) for the network output
+ * out[20], uniform-branch weight eps and plain step step_m. */
+double orc_learned_logp(const double *out, int64_t Dx, int64_t Dy, uint32_t step_m, float eps);
+/* n proposals from the fixed output out[20], draw i using the words of
+ * counter (sweep 0, cell i, trial 0) under key seed: D[2n] (0 where the
+ * Gaussian draw failed), drawn[n] (may be NULL) and ln P(D) (NaN where the
+ * draw failed; may be NULL). */
+void orc_learned_proposals(const double *out, uint32_t step_m, float eps, uint64_t seed,
+                           uint32_t n, int64_t *D, uint8_t *drawn, double *logp);
+/* k sweeps whose trials use the learned proposal with the fp64 network
+ * params[7060] and the Metropolis-Hastings acceptance. */
+void orc_sweep_learned(orc_box *b, const double *params, float eps, uint64_t k);
+/* k plain sweeps (cell order 0) that record every accepted move as the
+ * features at the old position, F[24], and the displacement, D[2]; the
+ * first cap moves are stored.  Returns the number of accepted moves. */
+uint64_t orc_sweep_collect(orc_box *b, uint64_t k, float *F, float *D, uint64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,13 @@ def lib():
         L.orc_nll_grad.argtypes = [f64p, f64p, f64p, C.c_uint32, f64p]
         L.orc_nll_grad.restype = C.c_double
         L.orc_adam.argtypes = [f64p, f64p, f64p, f64p, C.c_uint32, C.c_double, C.c_uint32]
+        L.orc_learned_logp.argtypes = [f64p, C.c_int64, C.c_int64, C.c_uint32, C.c_float]
+        L.orc_learned_logp.restype = C.c_double
+        L.orc_learned_proposals.argtypes = [f64p, C.c_uint32, C.c_float, C.c_uint64, C.c_uint32,
+                                            i64p, u8p, f64p]
+        L.orc_sweep_learned.argtypes = [p, f64p, C.c_float, C.c_uint64]
+        L.orc_sweep_collect.argtypes = [p, C.c_uint64, f32p, f32p, C.c_uint64]
+        L.orc_sweep_collect.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -156,6 +163,23 @@ def nll_grad(params, F, D):
 
 def adam(params, m, v, g, lr, t):
     lib().orc_adam(params, m, v, np.ascontiguousarray(g, np.float64), len(params), lr, t)
+
+
+def learned_logp(out, Dx, Dy, step_m, eps):
+    """ln P(D | out) of the learned proposal's lattice law."""
+    return lib().orc_learned_logp(np.ascontiguousarray(out, np.float64), int(Dx), int(Dy),
+                                  step_m, eps)
+
+
+def learned_proposals(out, step_m, eps, seed, n):
+    """n draws from the fixed output `out`: (D[n, 2] int64, drawn[n] bool,
+    ln P(D)[n])."""
+    D = np.zeros(2 * n, np.int64)
+    drawn = np.zeros(n, np.uint8)
+    lp = np.zeros(n, np.float64)
+    lib().orc_learned_proposals(np.ascontiguousarray(out, np.float64), step_m, eps, seed, n, D,
+                                drawn, lp)
+    return D.reshape(n, 2), drawn.astype(bool), lp
 
 
 class OracleBox:
@@ -275,6 +299,17 @@ class OracleBox:
         if lib().orc_cq(self.h, qx, qy, dr, B, num, cnt) != 0:
             raise ValueError("bins out of range")
         return num, cnt
+
+    def sweep_learned(self, params, eps, k=1):
+        lib().orc_sweep_learned(self.h, np.ascontiguousarray(params, np.float64), eps, k)
+
+    def sweep_collect(self, k, cap):
+        """k plain sweeps recording accepted moves: (F[n, 24], D[n, 2], total)."""
+        F = np.zeros(cap * 24, np.float32)
+        D = np.zeros(cap * 2, np.float32)
+        tot = int(lib().orc_sweep_collect(self.h, k, F, D, cap))
+        n = min(tot, cap)
+        return F.reshape(cap, 24)[:n], D.reshape(cap, 2)[:n], tot
 
     def features(self, cell, self_tag, x, y):
         f = np.zeros(24, np.float32)

@@ -32,3 +32,15 @@ def features(seed, B):
 def moves(seed, B, d=0.1):
     rng = np.random.default_rng(seed)
     return rng.uniform(-d, d, size=(B, 2))
+
+
+def mlp_outputs(seed):
+    """A network output vector (20 numbers) shaped like a trained one: logits
+    of order 1, means within 0.2 sigma, log widths around ln 0.05."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(20)
+    for k in range(4):
+        out[5 * k] = rng.standard_normal()
+        out[5 * k + 1: 5 * k + 3] = rng.uniform(-0.2, 0.2, 2)
+        out[5 * k + 3: 5 * k + 5] = np.log(0.05) + 0.5 * rng.standard_normal(2)
+    return out.astype(np.float32).astype(np.float64)
