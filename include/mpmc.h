@@ -369,12 +369,12 @@ int mpmc_batch_set_graphs(mpmc_batch b, uint32_t sweeps_per_graph);
  *  network: 24 -> 64 -> 64 -> 20 with SiLU; parameters (7060 floats) in the
  *    order W1[64][24], b1[64], W2[64][64], b2[64], W3[20][64], b3[20];
  *    output k (0..3) = (logit, mu_x, mu_y, a_x, a_y) at 5k..5k+4, component
- *    width exp(clamp(a, -7, 1)); BF16 weights, FP32 accumulation.
- *  proposal: q(delta) = eps U(delta) + (1 - eps) sum_k pi_k N(delta; mu_k,
- *    diag(s_k^2)), U uniform over the lattice steps in [-d, d]^2; delta is
- *    rounded to the q lattice.
- *  acceptance: min(1, q(-delta | f(x')) / q(delta | f(x))) if x' stays in
- *    its cell and overlaps no disk.
+ *    width exp(clamp(a, -10, 1)); BF16 weights, FP32 accumulation.
+ *  proposal: a mixture of the plain step (weight eps) and the network's
+ *    Gaussian mixture, as a law on the q lattice (written out below at
+ *    mpmc_learned_propose).
+ *  acceptance: min(1, P(-D | f(x')) / P(D | f(x))) if x' stays in its cell
+ *    and overlaps no disk.
  * Boxes swept with the learned proposal need cells of width >= 3 sigma
  * (mpmc_params.cell_min = 3): the 3 sigma neighbourhoods of x and x' then
  * lie in cells that no other thread moves during the colour sub-sweep. */
@@ -390,12 +390,13 @@ int mpmc_learner_free(mpmc_learner l);
 int mpmc_learner_set_params(mpmc_learner l, const float *params);
 int mpmc_learner_get_params(mpmc_learner l, float *params);
 /* Runs `sweeps` plain sweeps of box b (cell_min >= 3; same trajectory as
- * mpmc_sweep with the simple schedule) and records every accepted move as
- * (features at the old position, delta).  *n_total: moves recorded so far
+ * mpmc_sweep) and records every accepted move as (features at the old
+ * position, delta).  *n_total: moves recorded so far
  * (at most capacity). */
 int mpmc_learner_collect(mpmc_learner l, mpmc_box b, uint64_t sweeps, uint64_t *n_total);
-/* `steps` Adam steps (lr; beta 0.9/0.999) on minibatches of `batch` moves
- * drawn with replacement by Philox; loss = mean -log q_GMM(delta | f).
+/* `steps` Adam steps (lr; beta 0.9/0.999, eps 1e-8) on minibatches of
+ * `batch` moves drawn with replacement by Philox; loss = mean
+ * -log q_GMM(delta | f), the continuous mixture density.
  * *mean_loss: the loss of the last minibatch. */
 int mpmc_learner_train(mpmc_learner l, uint32_t steps, uint32_t batch, float lr, double *mean_loss);
 /* Diagnostics on host arrays: network outputs out[B][20] for F[B][24];
@@ -415,6 +416,43 @@ int mpmc_learned_features(mpmc_box b, const uint32_t *tags, uint32_t n, float *F
  * uniform fallback); counts as mpmc_sweep. */
 int mpmc_sweep_learned(mpmc_box b, mpmc_learner l, uint64_t k, float eps, uint64_t *trials,
                        uint64_t *accepts);
+
+/* The proposal as a law on the q lattice.  A trial proposes an integer
+ * displacement D = (Dx, Dy) (delta = D q) with probability
+ *   P(D) = e U(D) + (1 - e) G(D),  e = E / 2^32, E = nearest integer to
+ *          eps 2^32 (the branch compares a 32-bit word with E);
+ *   U(D): the plain trial's step, per axis D = step_m j with j odd,
+ *         |j| <= 2^14 - 1, probability 2^-14 each;
+ *   G(D): component k with probability pi_k, a point of N(mu_k,
+ *         diag(s_k^2)) drawn in double precision from 53-bit uniforms and
+ *         rounded to the nearest lattice point; a draw with |D| > 2^22 - 1
+ *         on an axis fails (the trial is rejected).  A lattice point's
+ *         probability is the Gaussian mass of its cell [D - 1/2, D + 1/2] q,
+ *         per axis (q/s) phi(u)(1 + h^2 He2(u)/6 + h^4 He4(u)/120),
+ *         u = (D q - mu)/s, h = q/(2 s).
+ * Acceptance: min(1, P(-D | out(x')) / P(D | out(x))) against a 53-bit
+ * uniform.  Random words of trial t in cell c, sweep k: stream 0 (disk,
+ * uniform step as in the plain trial, branch), stream 2 (component and
+ * acceptance uniforms), stream 4 (the Gaussian pair).  With eps = 1 the
+ * learned sweep is the plain sweep, word for word.
+ *
+ * Diagnostics of that law on host arrays (they allocate device memory for
+ * the call): mpmc_learned_propose draws n proposals from one fixed network
+ * output out[20], draw i with the words of counter (sweep 0, cell i,
+ * trial 0) under key seed, into D[2n] (0 where the draw failed), drawn[n]
+ * and logp[n] = ln P(D) (NaN where the draw failed); mpmc_learned_logp gives
+ * logp[i] = ln P(D_i | out_i) for out[n][20], D[n][2] (-inf below 1e-300).
+ * MPMC_EINVAL for n = 0, step_m outside 1..255 or eps outside [0, 1]. */
+int mpmc_learned_propose(const float *out, uint32_t step_m, float eps, uint64_t seed, uint32_t n,
+                         int32_t *D, uint8_t *drawn, double *logp);
+int mpmc_learned_logp(const float *out, const int32_t *D, uint32_t n, uint32_t step_m, float eps,
+                      double *logp);
+/* Diagnostics of the learner: recorded moves first..first+n-1 into host
+ * arrays F[n][24], D[n][2] (recording order follows the device's atomic
+ * counter; MPMC_EINVAL beyond the moves recorded); one Adam step with the
+ * given gradient (MPMC_MLP_PARAMS floats) and learning rate. */
+int mpmc_learner_moves(mpmc_learner l, uint64_t first, uint64_t n, float *F, float *D);
+int mpmc_learner_adam_step(mpmc_learner l, const float *grad, float lr);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *mpmc_last_error(void);

@@ -264,12 +264,15 @@ __device__ inline void mlp_infer_wave(const InferW &W, const uint16_t *X, float 
 }
 
 // ---------------------------------------------------------------------------
-// Mixture density and sampling (one lane, one sample).
+// The mixture for training (fp32): component k of the network output is
+// (logit, mu_x, mu_y, a_x, a_y) at 5k..5k+4, width s = exp(clamp(a)).
+constexpr float kAMin = -10.0f, kAMax = 1.0f;
+
 struct Gmm {
     float lw[4], mx[4], my[4], ax[4], ay[4];
 };
 
-__device__ inline float clampa(float a) { return fminf(fmaxf(a, -7.0f), 1.0f); }
+__device__ inline float clampa(float a) { return a < kAMin ? kAMin : (a > kAMax ? kAMax : a); }
 
 __device__ inline Gmm gmm_from(const float *o) {
     Gmm g;
@@ -291,29 +294,127 @@ __device__ inline Gmm gmm_from(const float *o) {
     return g;
 }
 
-__device__ inline float log_gmm(const Gmm &g, float dx, float dy) {
-    float l[4], best = -INFINITY;
+// ---------------------------------------------------------------------------
+// The proposal as a law on the q lattice of displacements D (delta = D q):
+//
+//   P(D) = e U(D) + (1 - e) G(D),   e = E / 2^32 exactly,
+//
+// U: the plain trial's step (per axis D = m j, j odd, |j| <= 2^14 - 1, each
+// with probability 2^-14); G: component k with probability pi_k, a point of
+// N(mu_k, diag(s_k^2)) drawn in double precision from 53-bit uniforms
+// (Box-Muller) and rounded to the nearest lattice point, draws with
+// |D| > 2^22 - 1 on an axis failing.  The probability of a lattice point
+// under one component is the Gaussian mass of its cell, per axis
+// (q/s) phi(u) (1 + c), u = (D q - mu)/s, c = h^2 He2(u)/6 + h^4 He4(u)/120,
+// h = q/(2s) (even Taylor terms of the cell integral; the next is below
+// 2e-14 relative for s >= e^-10 and |u| <= 9).  Everything after the
+// network's fp32 outputs is double precision, and the Metropolis-Hastings
+// ratio is the ratio of these lattice probabilities.
+//
+// Words of trial t in cell c, sweep k: A (stream 0): A.w0 selects the disk,
+// A.w1 and A.w2 give the uniform step (as in the plain trial), A.w3 < E
+// takes U; B (stream 2): (w0, w1) the component uniform, (w2, w3) the
+// acceptance uniform; C (stream 4): (w0, w1) u1 in (0, 1], (w2, w3) u2 in
+// [0, 1).  A 53-bit uniform from (hi, lo) is ((hi << 21) | (lo >> 11)) 2^-53.
+struct Mix {
+    double pi[4];        // component weights
+    double mx[4], my[4]; // means
+    double isx[4], isy[4];  // 1 / s
+    float ax[4], ay[4];  // clamped log widths
+};
+
+__device__ inline Mix mix_from(const float *o) {
+    Mix g;
+    double lmax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lmax = (double)o[5 * k] > lmax ? (double)o[5 * k] : lmax;
+    double z = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float ux = (dx - g.mx[k]) * expf(-g.ax[k]), uy = (dy - g.my[k]) * expf(-g.ay[k]);
-        l[k] = g.lw[k] - 1.8378770664093453f - g.ax[k] - g.ay[k] - 0.5f * (ux * ux + uy * uy);
-        best = fmaxf(best, l[k]);
+        g.pi[k] = exp((double)o[5 * k] - lmax);
+        z += g.pi[k];
     }
-    float s = 0.0f;
+    const double iz = 1.0 / z;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s += expf(l[k] - best);
-    return best + logf(s);
+    for (int k = 0; k < 4; ++k) {
+        g.pi[k] *= iz;
+        g.mx[k] = (double)o[5 * k + 1];
+        g.my[k] = (double)o[5 * k + 2];
+        g.ax[k] = clampa(o[5 * k + 3]);
+        g.ay[k] = clampa(o[5 * k + 4]);
+        g.isx[k] = exp(-(double)g.ax[k]);
+        g.isy[k] = exp(-(double)g.ay[k]);
+    }
+    return g;
 }
 
-// log q(delta) of the defensive mixture; the uniform part is the discrete
-// uniform law over the (2 D + 1)^2 lattice steps in [-d, d]^2 divided by q^2.
-__device__ inline float log_q(const Gmm &g, float dx, float dy, int Dx, int Dy, int Dm, float eps,
-                              float log_u) {
-    const float lg = logf(1.0f - eps) + log_gmm(g, dx, dy);
-    if (abs(Dx) > Dm || abs(Dy) > Dm || eps <= 0.0f) return lg;
-    const float lu = logf(eps) + log_u;
-    const float mx = fmaxf(lg, lu);
-    return mx + logf(expf(lg - mx) + expf(lu - mx));
+__device__ inline double u53(uint32_t hi, uint32_t lo) {
+    return (double)(((uint64_t)hi << 21) | (lo >> 11)) * 0x1p-53;
+}
+
+__device__ inline bool on_step_lattice(int D, uint32_t m) {
+    const int j = D / (int)m;
+    return j * (int)m == D && (j & 1) != 0 && (j < 0 ? -j : j) <= 16383;
+}
+
+// (1 + c) of one axis, with u the normalised offset and is = 1 / s.
+__device__ inline double cell_factor(double u2, double is) {
+    const double h = (0.5 * kQd) * is;
+    const double h2 = h * h;
+    const double he2 = u2 - 1.0, he4 = (u2 - 6.0) * u2 + 3.0;
+    const double c = h2 * he2 * (1.0 / 6.0) + (h2 * h2) * he4 * (1.0 / 120.0);
+    return 1.0 + c;
+}
+
+// P(D) of the lattice law (probabilities below 1e-300 round to 0).
+__device__ inline double lattice_p(const Mix &g, int Dx, int Dy, uint32_t m, double e) {
+    double pu = (on_step_lattice(Dx, m) && on_step_lattice(Dy, m)) ? 0x1p-28 : 0.0;
+    double pg = 0.0;
+    if ((Dx < 0 ? -Dx : Dx) <= 4194303 && (Dy < 0 ? -Dy : Dy) <= 4194303) {
+        const double dx = (double)Dx * kQd, dy = (double)Dy * kQd;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double ux = (dx - g.mx[k]) * g.isx[k], uy = (dy - g.my[k]) * g.isy[k];
+            const double ux2 = ux * ux, uy2 = uy * uy;
+            pg += g.pi[k] * (g.isx[k] * g.isy[k]) * exp(-0.5 * (ux2 + uy2)) *
+                  (cell_factor(ux2, g.isx[k]) * cell_factor(uy2, g.isy[k]));
+        }
+        pg *= kQd * kQd * (1.0 / 6.283185307179586);
+    }
+    return e * pu + (1.0 - e) * pg;
+}
+
+// Draws D with the words A, B, C; false for a failed Gaussian draw.
+__device__ inline bool lattice_draw(const Mix &g, const Words &A, const Words &B, const Words &C,
+                                    uint32_t m, uint64_t E, int &Dx, int &Dy) {
+    if ((uint64_t)A.w3 < E) {
+        Dx = (int)m * (2 * (int)(A.w1 >> 18) + 1 - 16384);
+        Dy = (int)m * (2 * (int)(A.w2 >> 18) + 1 - 16384);
+        return true;
+    }
+    const double uc = u53(B.w0, B.w1);
+    int k = 3;
+    double cum = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cum += g.pi[c];
+        if (k == 3 && uc < cum) k = c;
+    }
+    const double u1 = (double)((((uint64_t)C.w0 << 21) | (C.w1 >> 11)) + 1) * 0x1p-53;
+    const double u2 = u53(C.w2, C.w3);
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(6.283185307179586 * u2, &sn, &cs);
+    const double mx = k == 0 ? g.mx[0] : k == 1 ? g.mx[1] : k == 2 ? g.mx[2] : g.mx[3];
+    const double my = k == 0 ? g.my[0] : k == 1 ? g.my[1] : k == 2 ? g.my[2] : g.my[3];
+    const float ax = k == 0 ? g.ax[0] : k == 1 ? g.ax[1] : k == 2 ? g.ax[2] : g.ax[3];
+    const float ay = k == 0 ? g.ay[0] : k == 1 ? g.ay[1] : k == 2 ? g.ay[2] : g.ay[3];
+    const double tx = (mx + (exp((double)ax) * r) * cs) * 4194304.0;
+    const double ty = (my + (exp((double)ay) * r) * sn) * 4194304.0;
+    if (!(fabs(tx) < 4194303.5 && fabs(ty) < 4194303.5)) return false;
+    Dx = (int)rint(tx);
+    Dy = (int)rint(ty);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -444,7 +545,8 @@ __device__ inline int lane_features(const uint8_t *cnt, const float *px, const f
 // its cell's trials; the two network evaluations of a trial are wave-wide.
 struct LearnView {
     const PackedW *W;
-    float eps;
+    uint64_t E;                      // uniform branch: a 32-bit word below E
+    double e;                        // its probability, E / 2^32
     unsigned long long *nfeat_over;  // neighbourhoods with more than 12 disks
 };
 
@@ -509,8 +611,6 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     Nbhd nbh;
     if (valid) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
     const uint32_t n = valid ? (nbh.m >> 12) & 7u : 0u;
-    const int Dm = (int)v.step_m << 14;  // d in q units
-    const float log_u = -2.0f * logf((float)(2 * Dm + 1) * kQ);
     float *scr = P.so + kSS * lane;  // scratch before the MLP
     uint32_t trials = 0, accepts = 0;
     uint32_t perm = 0x76543210u;
@@ -531,14 +631,14 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     }
     for (uint32_t tr = 0; tr < v.n_trial; ++tr) {
         const bool act = n > 0;
-        Words w4{0, 0, 0, 0}, w2{0, 0, 0, 0};
+        Words wa{0, 0, 0, 0}, wb{0, 0, 0, 0};
         uint32_t slot = 0;
         float x = 0.0f, y = 0.0f;
         if (act && tr > 0) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
         if (act) {
-            w4 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
-            w2 = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
-            slot = (v.n_trial == 1) ? mulhi32(w4.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
+            wa = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
+            wb = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
+            slot = (v.n_trial == 1) ? mulhi32(wa.w0, n) : (perm >> (4 * (tr % n))) & 0xFu;
             x = slot == 0 ? nbh.x[4][0] : slot == 1 ? nbh.x[4][1] : v.x_out[slot_at(cell, slot, M * M)];
             y = slot == 0 ? nbh.y[4][0] : slot == 1 ? nbh.y[4][1] : v.y_out[slot_at(cell, slot, M * M)];
         }
@@ -555,38 +655,18 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         if (tr == 0) __syncthreads();  // the weights are in LDS
         float *OUT = P.so;
         mlp_infer_wave(L.w, P.X, OUT);
-        // propose
-        Gmm g = gmm_from(OUT + kOS * lane);
-        const uint32_t eps_u = (uint32_t)fminf(lv.eps * 4294967296.0f, 4294967295.0f);
-        int Dx, Dy;
-        bool drawn = true;  // a Gaussian draw beyond +-1 sigma per axis is rejected
-        if (w4.w1 < eps_u) {
-            Dx = (int)mulhi32(w4.w2, 2u * (uint32_t)Dm + 1u) - Dm;
-            Dy = (int)mulhi32(w4.w3, 2u * (uint32_t)Dm + 1u) - Dm;
-        } else {
-            const float uk = (float)(w2.w0 >> 8) * (1.0f / 16777216.0f);
-            int k = 3;
-            float cum = 0.0f;
-            for (int c = 0; c < 3; ++c) {
-                cum += expf(g.lw[c]);
-                if (uk < cum) { k = c; break; }
-            }
-            const float u1 = (float)((w2.w1 >> 8) + 1u) * (1.0f / 16777216.0f);
-            const float u2 = (float)(w2.w2 >> 8) * (1.0f / 16777216.0f);
-            const float rr = sqrtf(-2.0f * logf(u1));
-            float sn, cs;
-            sincosf(6.283185307179586f * u2, &sn, &cs);
-            const float ddx = g.mx[k] + expf(g.ax[k]) * rr * cs;
-            const float ddy = g.my[k] + expf(g.ay[k]) * rr * sn;
-            // rejecting (not clamping) draws beyond the range keeps the
-            // proposal probability of every accepted step equal to q^2 times
-            // the density the Metropolis-Hastings ratio uses
-            drawn = fabsf(ddx) < 1.0f && fabsf(ddy) < 1.0f;
-            Dx = drawn ? (int)rintf(ddx * 4194304.0f) : 0;
-            Dy = drawn ? (int)rintf(ddy * 4194304.0f) : 0;
+        // propose D from the lattice law and keep P(D)
+        int Dx = 0, Dy = 0;
+        bool drawn = false;
+        double pf = 1.0;
+        if (act) {
+            const Mix g = mix_from(OUT + kOS * lane);
+            const Words wc = (uint64_t)wa.w3 < lv.E
+                                 ? Words{0, 0, 0, 0}
+                                 : draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamGauss);
+            drawn = lattice_draw(g, wa, wb, wc, v.step_m, lv.E, Dx, Dy);
+            if (drawn) pf = lattice_p(g, Dx, Dy, v.step_m, lv.e);
         }
-        const float dxf = (float)Dx * kQ, dyf = (float)Dy * kQ;
-        const float lq_f = log_q(g, dxf, dyf, Dx, Dy, Dm, lv.eps, log_u);
         // geometry in q units: exact
         const int U = (int)(x * 4194304.0f) + Dx, V = (int)(y * 4194304.0f) + Dy;
         bool ok = act && drawn && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
@@ -594,7 +674,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         if (ok)
             for_each_other(nbh, v.x_out, v.y_out, v.w, slot, xn, yn,
                            [&](float ddx, float ddy) { ok = ok && !overlap_f32(ddx, ddy); });
-        // reverse density at x' (every lane takes part in the wave GEMMs)
+        // reverse law at x' (every lane takes part in the wave GEMMs)
         wave_sync();
         if (ok) {
             lane_features(nbh, v.x_out, v.y_out, v.w, slot, xn, yn, scr, P.X + kXS * lane, nullptr);
@@ -605,10 +685,10 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         mlp_infer_wave(L.w, P.X, OUT);
         if (act) ++trials;
         if (ok) {
-            const Gmm gr = gmm_from(OUT + kOS * lane);
-            const float lq_r = log_q(gr, -dxf, -dyf, -Dx, -Dy, Dm, lv.eps, log_u);
-            const float ua = ((float)(w2.w3 >> 8) + 0.5f) * (1.0f / 16777216.0f);
-            if (logf(ua) < lq_r - lq_f) {
+            const Mix gr = mix_from(OUT + kOS * lane);
+            const double pr = lattice_p(gr, -Dx, -Dy, v.step_m, lv.e);
+            // min(1, pr / pf) against the 53-bit acceptance uniform
+            if (pr >= pf || u53(wb.w2, wb.w3) * pf < pr) {
                 v.x_out[slot_at(cell, slot, M * M)] = xn;
                 v.y_out[slot_at(cell, slot, M * M)] = yn;
                 ++accepts;
@@ -788,8 +868,8 @@ __global__ void __launch_bounds__(64) k_train(TrainView tv) {
         const float lse = best + logf(s);
         for (int k = 0; k < 4; ++k) {
             const float r = expf(l[k] - lse), pk = expf(g.lw[k]);
-            const float inx = (o[5 * k + 3] > -7.0f && o[5 * k + 3] < 1.0f) ? 1.0f : 0.0f;
-            const float iny = (o[5 * k + 4] > -7.0f && o[5 * k + 4] < 1.0f) ? 1.0f : 0.0f;
+            const float inx = (o[5 * k + 3] > kAMin && o[5 * k + 3] < kAMax) ? 1.0f : 0.0f;
+            const float iny = (o[5 * k + 4] > kAMin && o[5 * k + 4] < kAMax) ? 1.0f : 0.0f;
             dout[5 * k] = (pk - r) * inv;
             dout[5 * k + 1] = -r * ux[k] * expf(-g.ax[k]) * inv;
             dout[5 * k + 2] = -r * uy[k] * expf(-g.ay[k]) * inv;
@@ -959,6 +1039,32 @@ __global__ void k_adam(float *p, float *m, float *vv, float *grad, PackedW *W, u
     }
 }
 
+// Diagnostics of the lattice law: n draws from one fixed network output with
+// the words of counter (sweep 0, cell i, trial 0), and P(D) at given points.
+__global__ void k_lattice_propose(const float *out, uint32_t m, uint64_t E, double e, uint32_t k0,
+                                  uint32_t k1, uint32_t n, int32_t *D, uint8_t *drawn, double *lp) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Mix g = mix_from(out);
+    const Words A = draw(k0, k1, 0, i, 0, kStreamTrial);
+    const Words B = draw(k0, k1, 0, i, 0, kStreamLearned);
+    const Words Cw = draw(k0, k1, 0, i, 0, kStreamGauss);
+    int Dx = 0, Dy = 0;
+    const bool ok = lattice_draw(g, A, B, Cw, m, E, Dx, Dy);
+    D[2 * i] = ok ? Dx : 0;
+    D[2 * i + 1] = ok ? Dy : 0;
+    drawn[i] = ok ? 1 : 0;
+    lp[i] = ok ? log(lattice_p(g, Dx, Dy, m, e)) : __builtin_nan("");
+}
+
+__global__ void k_lattice_p(const float *out, const int32_t *D, uint32_t n, uint32_t m, double e,
+                            double *lp) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Mix g = mix_from(out + (size_t)20 * i);
+    lp[i] = log(lattice_p(g, D[2 * i], D[2 * i + 1], m, e));
+}
+
 }  // namespace mpmc
 
 // ===========================================================================
@@ -971,6 +1077,12 @@ using namespace mpmc;
         if (e_ != hipSuccess)                                                            \
             return fail(MPMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));           \
     } while (0)
+
+// E: the uniform branch is taken when a 32-bit word is below E, the
+// nearest integer to eps 2^32 (0 <= E <= 2^32).
+static uint64_t branch_threshold(float eps) {
+    return (uint64_t)llrint((double)eps * 4294967296.0);
+}
 
 namespace {
 struct Learner {
@@ -1273,7 +1385,8 @@ extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, floa
                                   (int)lds);
         attr = true;
     }
-    LearnView lv{l->W, eps, l->over};
+    const uint64_t E = branch_threshold(eps);
+    LearnView lv{l->W, E, ldexp((double)E, -32), l->over};
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
     for (uint64_t s = 0; s < k; ++s) {
         BoxView v = b->view(b->cur);
@@ -1307,5 +1420,95 @@ extern "C" int mpmc_learner_info(mpmc_learner lh, uint64_t *n_data, uint64_t *n_
     if (n_data) *n_data = c[0] < l->cap ? c[0] : l->cap;
     if (n_feature_overflow) *n_feature_overflow = c[1];
     if (steps) *steps = l->step;
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_moves(mpmc_learner lh, uint64_t first, uint64_t n, float *F, float *D) {
+    if (!lh || (n && (!F || !D))) return fail(MPMC_EINVAL, "bad arguments");
+    Learner *l = LR(lh);
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, l->count, 8, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipStreamSynchronize(l->stream));
+    const uint64_t have = c < l->cap ? c : l->cap;
+    if (first > have || n > have - first) return fail(MPMC_EINVAL, "moves %llu..%llu of %llu",
+                                                      (unsigned long long)first,
+                                                      (unsigned long long)(first + n),
+                                                      (unsigned long long)have);
+    if (n == 0) return MPMC_OK;
+    HIPCHK(hipMemcpyAsync(F, l->F + first * 24, n * 24 * 4, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipMemcpyAsync(D, l->D + first * 2, n * 2 * 4, hipMemcpyDeviceToHost, l->stream));
+    HIPCHK(hipStreamSynchronize(l->stream));
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learner_adam_step(mpmc_learner lh, const float *grad, float lr) {
+    if (!lh || !grad) return fail(MPMC_EINVAL, "NULL argument");
+    Learner *l = LR(lh);
+    HIPCHK(hipMemcpyAsync(l->grad, grad, kNPARAM * 4, hipMemcpyHostToDevice, l->stream));
+    ++l->step;
+    k_adam<<<(kNPARAM + 255) / 256, 256, 0, l->stream>>>(l->p, l->m, l->v, l->grad, l->W, l->step, lr, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(l->stream));
+    return MPMC_OK;
+}
+
+// Device buffers of a diagnostic call, released on every path.
+namespace {
+struct DiagBufs {
+    std::vector<void *> p;
+    ~DiagBufs() {
+        for (void *q : p) (void)hipFree(q);
+    }
+    hipError_t get(void **q, size_t bytes) {
+        hipError_t e = hipMalloc(q, bytes ? bytes : 4);
+        if (e == hipSuccess) p.push_back(*q);
+        return e;
+    }
+};
+}  // namespace
+
+extern "C" int mpmc_learned_propose(const float *out, uint32_t step_m, float eps, uint64_t seed,
+                                    uint32_t n, int32_t *D, uint8_t *drawn, double *logp) {
+    if (!out || !D || !drawn || !logp || n == 0) return fail(MPMC_EINVAL, "bad arguments");
+    if (step_m == 0 || step_m > 255) return fail(MPMC_EINVAL, "step_m must be in 1..255");
+    if (!(eps >= 0.0f) || eps > 1.0f) return fail(MPMC_EINVAL, "eps must be in [0, 1]");
+    DiagBufs B;
+    float *dout = nullptr;
+    int32_t *dD = nullptr;
+    uint8_t *dd = nullptr;
+    double *dl = nullptr;
+    HIPCHK(B.get((void **)&dout, 20 * 4));
+    HIPCHK(B.get((void **)&dD, (size_t)n * 8));
+    HIPCHK(B.get((void **)&dd, n));
+    HIPCHK(B.get((void **)&dl, (size_t)n * 8));
+    HIPCHK(hipMemcpy(dout, out, 20 * 4, hipMemcpyHostToDevice));
+    const uint64_t E = branch_threshold(eps);
+    k_lattice_propose<<<(n + 255) / 256, 256>>>(dout, step_m, E, ldexp((double)E, -32), (uint32_t)seed,
+                                                (uint32_t)(seed >> 32), n, dD, dd, dl);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(D, dD, (size_t)n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(drawn, dd, n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(logp, dl, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_learned_logp(const float *out, const int32_t *D, uint32_t n, uint32_t step_m,
+                                 float eps, double *logp) {
+    if (!out || !D || !logp || n == 0) return fail(MPMC_EINVAL, "bad arguments");
+    if (step_m == 0 || step_m > 255) return fail(MPMC_EINVAL, "step_m must be in 1..255");
+    if (!(eps >= 0.0f) || eps > 1.0f) return fail(MPMC_EINVAL, "eps must be in [0, 1]");
+    DiagBufs B;
+    float *dout = nullptr;
+    int32_t *dD = nullptr;
+    double *dl = nullptr;
+    HIPCHK(B.get((void **)&dout, (size_t)n * 20 * 4));
+    HIPCHK(B.get((void **)&dD, (size_t)n * 8));
+    HIPCHK(B.get((void **)&dl, (size_t)n * 8));
+    HIPCHK(hipMemcpy(dout, out, (size_t)n * 20 * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dD, D, (size_t)n * 8, hipMemcpyHostToDevice));
+    const uint64_t E = branch_threshold(eps);
+    k_lattice_p<<<(n + 255) / 256, 256>>>(dout, dD, n, step_m, ldexp((double)E, -32), dl);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(logp, dl, (size_t)n * 8, hipMemcpyDeviceToHost));
     return MPMC_OK;
 }

@@ -12,8 +12,9 @@
 // counter (sweep_lo, cell, trial, (sweep_hi << 8) | stream):
 //   stream 0  trial words: w0 selects the disk, w1/w2 give the x/y step
 //   stream 1  in-cell shuffle words (n_trial > 1), trial field = word / 4
-//   stream 2  learned-proposal words
+//   stream 2  learned-proposal words: component and acceptance uniforms
 //   stream 3  cell = 0xFFFFFFFF: per-sweep shift x, shift y, colour order
+//   stream 4  learned-proposal words: the Gaussian pair
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,7 +24,8 @@ namespace mpmc {
 constexpr float kQ = 1.0f / 4194304.0f;  // 2^-22
 constexpr double kQd = 1.0 / 4194304.0;
 constexpr uint32_t kGlobalCell = 0xFFFFFFFFu;
-constexpr int kStreamTrial = 0, kStreamShuffle = 1, kStreamLearned = 2, kStreamGlobal = 3;
+constexpr int kStreamTrial = 0, kStreamShuffle = 1, kStreamLearned = 2, kStreamGlobal = 3,
+              kStreamGauss = 4;
 
 struct Words { uint32_t w0, w1, w2, w3; };
 

@@ -114,6 +114,10 @@ _SIGS = {
     "mpmc_learned_features": [_P, _P, C.c_uint32, _P],
     "mpmc_sweep_learned": [_P, _P, C.c_uint64, C.c_float, C.POINTER(C.c_uint64),
                            C.POINTER(C.c_uint64)],
+    "mpmc_learned_propose": [_P, C.c_uint32, C.c_float, C.c_uint64, C.c_uint32, _P, _P, _P],
+    "mpmc_learned_logp": [_P, _P, C.c_uint32, C.c_uint32, C.c_float, _P],
+    "mpmc_learner_moves": [_P, C.c_uint64, C.c_uint64, _P, _P],
+    "mpmc_learner_adam_step": [_P, _P, C.c_float],
 }
 
 
@@ -541,6 +545,21 @@ class Learner:
         _check(_lib.mpmc_learner_nll_grad(self.h, _ptr(F), _ptr(D), F.shape[0], _ptr(g), C.byref(loss)))
         return loss.value, g
 
+    def moves(self, first=0, n=None):
+        """Recorded moves first..first+n-1: (F[n, 24], D[n, 2])."""
+        if n is None:
+            n = self.info()["n_data"] - first
+        F = np.zeros((n, 24), np.float32)
+        D = np.zeros((n, 2), np.float32)
+        _check(_lib.mpmc_learner_moves(self.h, first, n, _ptr(F), _ptr(D)))
+        return F, D
+
+    def adam_step(self, grad, lr):
+        """One Adam step with the given gradient (diagnostic)."""
+        g = np.ascontiguousarray(grad, np.float32)
+        assert g.size == MLP_PARAMS
+        _check(_lib.mpmc_learner_adam_step(self.h, _ptr(g), lr))
+
     def info(self):
         n, o, s = C.c_uint64(), C.c_uint64(), C.c_uint32()
         _check(_lib.mpmc_learner_info(self.h, C.byref(n), C.byref(o), C.byref(s)))
@@ -559,6 +578,29 @@ def sweep_learned(box, learner, k=1, eps=0.1, counts=False):
     _check(load().mpmc_sweep_learned(box.h, learner.h, k, eps, C.byref(t) if counts else None,
                                      C.byref(a) if counts else None))
     return (t.value, a.value) if counts else None
+
+
+def learned_propose(out, step_m, eps, seed, n):
+    """n draws of the learned proposal's lattice law from one fixed network
+    output: (D[n, 2] int32, drawn[n] bool, ln P(D)[n])."""
+    o = np.ascontiguousarray(out, np.float32)
+    assert o.size == 20
+    D = np.zeros((n, 2), np.int32)
+    drawn = np.zeros(n, np.uint8)
+    lp = np.zeros(n, np.float64)
+    _check(load().mpmc_learned_propose(_ptr(o), step_m, eps, seed, n, _ptr(D), _ptr(drawn),
+                                       _ptr(lp)))
+    return D, drawn.astype(bool), lp
+
+
+def learned_logp(outs, D, step_m, eps):
+    """ln P(D_i | out_i) of the lattice law for outs[n, 20], D[n, 2]."""
+    o = np.ascontiguousarray(outs, np.float32).reshape(-1, 20)
+    d = np.ascontiguousarray(D, np.int32).reshape(-1, 2)
+    assert len(o) == len(d)
+    lp = np.zeros(len(o), np.float64)
+    _check(load().mpmc_learned_logp(_ptr(o), _ptr(d), len(o), step_m, eps, _ptr(lp)))
+    return lp
 
 
 def cq_bin_max(Cv, width):

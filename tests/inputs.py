@@ -44,3 +44,15 @@ def mlp_outputs(seed):
         out[5 * k + 1: 5 * k + 3] = rng.uniform(-0.2, 0.2, 2)
         out[5 * k + 3: 5 * k + 5] = np.log(0.05) + 0.5 * rng.standard_normal(2)
     return out.astype(np.float32).astype(np.float64)
+
+
+def fixed_output_params(seed, out):
+    """Network parameters (fp32 values) whose last layer has zero weights, so
+    that the output is the bias b3 = out whatever the features: the hidden
+    layers are random and still evaluated."""
+    p = mlp_params(seed).astype(np.float32)
+    b3 = NPARAM - 20
+    w3 = b3 - 20 * 64
+    p[w3:b3] = 0.0
+    p[b3:] = np.asarray(out, np.float32)
+    return p
