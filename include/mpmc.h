@@ -174,6 +174,20 @@ int mpmc_psi6_field(mpmc_box b, float *re, float *im, float *field_re, float *fi
  * MPMC_EINVAL for an index outside (-4096, 4096). */
 int mpmc_structure_factor(mpmc_box b, const int32_t *hk, uint32_t nq, double *S);
 
+/* mpmc_structure_factor for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc): hk (2 nq int32) and S (nq doubles) are DEVICE pointers, the
+ * work is enqueued on the box's stream and the call returns without waiting
+ * for it.  The per-workgroup partial sums live in a fixed 4 MiB device array
+ * of the library (one per device, held until the process ends) instead of
+ * the box's work buffer, so nothing is allocated: at most 4096 wave vectors
+ * per call (MPMC_EINVAL beyond).  A wave vector with an index outside
+ * (-4096, 4096) gets S = NaN.  Every call on one device shares the array:
+ * calls that may overlap on one device (different streams, or threads)
+ * race and must be serialised by the caller.  The call reads the box's
+ * device scalars to the host first (a synchronising copy, no allocation). */
+int mpmc_structure_factor_noalloc(mpmc_box b, const int32_t *hk, uint32_t nq, double *S);
+
 /* The first diffraction peak: of the allowed wave vectors q != 0 with
  * q_lo <= |q| <= q_hi and direction atan2(k, h) in [theta0, theta0 + dtheta)
  * modulo 2 pi (radians; dtheta >= 2 pi means every direction), the one with

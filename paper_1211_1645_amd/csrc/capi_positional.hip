@@ -3,6 +3,7 @@
 // the first diffraction peak q0, chi_j and its field, and C_q(r).
 #include <math.h>
 
+#include <mutex>
 #include <vector>
 
 #include "mpmc_host.hpp"
@@ -74,6 +75,68 @@ extern "C" int mpmc_structure_factor(mpmc_box bh, const int32_t *hk, uint32_t nq
             return fail(MPMC_EINVAL, "wave-vector index %d outside (-%d, %d)", hk[i], kMaxIndex,
                         kMaxIndex);
     return structure_factor(B(bh), hk, nq, S);
+}
+
+// ---------------------------------------------------------------------------
+// Structure factor without allocation.  The per-workgroup partial sums of
+// k_rho go to a fixed device array instead of the box's growable work
+// buffer: at most kNoAllocQ wave vectors per call, 64 workgroup rows each of
+// 16 bytes, 4 MiB held by every device the library runs on until the process
+// ends.  Host code never passes `scratch` itself to a kernel or copy (its
+// host-side name is not a device address): it uses the address that
+// hipGetSymbolAddress returns for the device, looked up once per device.
+namespace {
+constexpr uint32_t kNoAllocQ = 4096;
+constexpr size_t kScratchBytes = (size_t)64 * kNoAllocQ * 16;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The scratch address on the device of stream st (NULL: the current device).
+static int scratch_on(hipStream_t st, void **out) {
+    int cur = 0, dev = 0;
+    HIPCHK(hipGetDevice(&cur));
+    dev = cur;
+    if (st) HIPCHK(hipStreamGetDevice(st, &dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MPMC_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        if (dev != cur) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess)
+            return fail(MPMC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_structure_factor_noalloc(mpmc_box bh, const int32_t *hk, uint32_t nq,
+                                             double *S) {
+    if (!bh) return fail(MPMC_EINVAL, "NULL box");
+    if (nq == 0) return MPMC_OK;
+    if (!hk || !S) return fail(MPMC_EINVAL, "NULL wave-vector or output array");
+    if (nq > kNoAllocQ)
+        return fail(MPMC_EINVAL, "%u wave vectors: at most %u per call without allocation", nq,
+                    kNoAllocQ);
+    Box *b = B(bh);
+    void *work = nullptr;
+    int rc = scratch_on(b->stream, &work);
+    if (rc) return rc;
+    rc = b->read_scalars();  // the accumulated shift places the disks
+    if (rc) return rc;
+    const MeasureView m = b->mview();
+    if (rho_work_bytes(m, nq) > kScratchBytes)
+        return fail(MPMC_EINVAL, "partials of %zu bytes exceed the %zu-byte scratch",
+                    rho_work_bytes(m, nq), kScratchBytes);
+    launch_structure_factor(m, hk, nq, S, work, b->stream);
+    HIPCHK(hipGetLastError());
+    return MPMC_OK;
 }
 
 extern "C" int mpmc_find_q0(mpmc_box bh, double q_lo, double q_hi, double theta0, double dtheta,

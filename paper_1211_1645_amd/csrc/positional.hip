@@ -112,11 +112,19 @@ __global__ void __launch_bounds__(256) k_rho(MeasureView m, const int32_t *hk, u
     }
 }
 
-// S(q) = |sum of the partials|^2 / N; one thread per wave vector.
-__global__ void k_rho_reduce(const double2 *part, uint32_t nbx, uint32_t nq, uint32_t N,
-                             double *S) {
+// S(q) = |sum of the partials|^2 / N; one thread per wave vector.  A wave
+// vector with an index outside (-4096, 4096), beyond the accuracy the phase
+// arithmetic is stated for, gets NaN (the host entry points reject such
+// indices before the launch; device arrays are checked here).
+__global__ void k_rho_reduce(const double2 *part, const int32_t *hk, uint32_t nbx, uint32_t nq,
+                             uint32_t N, double *S) {
     const uint32_t iq = blockIdx.x * blockDim.x + threadIdx.x;
     if (iq >= nq) return;
+    const int32_t h = hk[2 * iq], k = hk[2 * iq + 1];
+    if (h <= -4096 || h >= 4096 || k <= -4096 || k >= 4096) {
+        S[iq] = __builtin_nan("");
+        return;
+    }
     const uint32_t by = iq / kQC, j = iq % kQC;
     double a = 0.0, b = 0.0;
     for (uint32_t bx = 0; bx < nbx; ++bx) {
@@ -141,7 +149,7 @@ void launch_structure_factor(const MeasureView &m, const int32_t *hk, uint32_t n
     const uint32_t nbx = rho_split(m), nby = (nq + kQC - 1) / kQC;
     double2 *part = static_cast<double2 *>(work);
     k_rho<<<dim3(nbx, nby), 256, 0, st>>>(m, hk, nq, part);
-    k_rho_reduce<<<(nq + 255) / 256, 256, 0, st>>>(part, nbx, nq, m.N, S);
+    k_rho_reduce<<<(nq + 255) / 256, 256, 0, st>>>(part, hk, nbx, nq, m.N, S);
 }
 
 // ---------------------------------------------------------------------------

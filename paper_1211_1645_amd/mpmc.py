@@ -73,6 +73,7 @@ _SIGS = {
     "mpmc_measure_async": [_P, _P, C.c_int],
     "mpmc_measure_wait": [_P, C.POINTER(C.c_uint32)],
     "mpmc_structure_factor": [_P, _P, C.c_uint32, _P],
+    "mpmc_structure_factor_noalloc": [_P, _P, C.c_uint32, _P],
     "mpmc_find_q0": [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int32),
                      C.POINTER(C.c_int32), C.POINTER(C.c_double)],
     "mpmc_chi_field": [_P, C.c_int32, C.c_int32, _P, _P, _P, _P, C.c_int],
@@ -353,6 +354,17 @@ class Box:
         S = np.zeros(len(hk), np.float64)
         _check(_lib.mpmc_structure_factor(self.h, _ptr(hk), len(hk), _ptr(S)))
         return S
+
+    def structure_factor_noalloc(self, hk, S):
+        """S(q) into the float64 CUDA tensor S for the int32 CUDA tensor hk
+        of (h, k) pairs, with no device allocation; enqueued on the box's
+        stream."""
+        assert hk.is_cuda and S.is_cuda and hk.is_contiguous() and S.is_contiguous()
+        assert hk.element_size() == 4 and S.element_size() == 8 and S.dtype.is_floating_point
+        nq = hk.numel() // 2
+        assert S.numel() >= nq
+        _check(_lib.mpmc_structure_factor_noalloc(self.h, C.c_void_p(hk.data_ptr()), nq,
+                                                  C.c_void_p(S.data_ptr())))
 
     def find_q0(self, q_lo, q_hi, theta0=0.0, dtheta=2.0 * np.pi):
         """The allowed wave vector of largest S in the window; (h, k, S)."""
