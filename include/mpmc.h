@@ -333,6 +333,15 @@ int mpmc_tau(const double *C, uint32_t maxlag, double lo, double hi, double *tau
  * (fused tiles need cells of at most 4 disks and an even tile <= M). */
 int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t threads);
 
+/* Phase profile of the fused sweep kernel: runs `sweeps` sweeps (the chain
+ * advances exactly as with mpmc_sweep), each workgroup recording the device
+ * realtime clock at its phase boundaries, and returns in phase_us[8] the
+ * mean duration per tile in microseconds of: the region load, colour passes
+ * 1-4 (in sweep order), the re-bin's class counts, its scatter, and the
+ * whole tile.  Allocates a stamp buffer for the call.  MPMC_EINVAL unless
+ * the box runs the fused schedule. */
+int mpmc_profile_phases(mpmc_box b, uint32_t sweeps, double *phase_us);
+
 /* Long runs replay a captured HIP graph of this many sweeps (even, default
  * 128 fused / 32 simple); 0 launches every sweep directly. */
 int mpmc_set_graphs(mpmc_box b, uint32_t sweeps_per_graph);

@@ -547,6 +547,55 @@ extern "C" int mpmc_sweep(mpmc_box bh, uint64_t k, uint64_t *trials, uint64_t *a
     return MPMC_OK;
 }
 
+extern "C" int mpmc_profile_phases(mpmc_box bh, uint32_t sweeps, double *phase_us) {
+    if (!bh || !phase_us || sweeps == 0) return fail(MPMC_EINVAL, "bad arguments");
+    Box *b = B(bh);
+    if (b->in_batch) return fail(MPMC_ESTATE, "boxes of a batch are swept with mpmc_batch_sweep");
+    if (!b->placed) return fail(MPMC_ESTATE, "no configuration: call mpmc_set_positions first");
+    if (b->sched != MPMC_SCHED_FUSED)
+        return fail(MPMC_EINVAL, "phase profiles need the fused schedule");
+    const uint32_t nt = (b->g.M + b->shape.tile - 1) / b->shape.tile;
+    const size_t words = (size_t)nt * nt * 8;
+    unsigned long long *d = nullptr;
+    int rc = b->alloc_dev((void **)&d, words * 8);
+    if (rc) return rc;
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    std::vector<unsigned long long> h(words);
+    double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    rc = b->join_meas();
+    for (uint32_t k = 0; k < sweeps && rc == MPMC_OK && e == hipSuccess; ++k) {
+        // one sweep as mpmc_sweep launches it outside a graph, with stamps
+        BoxView v = b->view(b->cur);
+        if (k + 1 < sweeps) {
+            v.cnt_can = nullptr;
+            v.x_can = v.y_can = nullptr;
+            v.tag_can = nullptr;
+        }
+        launch_fused_sweep(v, b->shape, b->stream, d);
+        launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W,
+                       b->g.Lq, 1, b->stream);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, words * 8, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        b->cur ^= 1;
+        ++b->host_sweeps;
+        b->canon_in_c = true;
+        for (size_t t = 0; t < (size_t)nt * nt; ++t) {
+            const unsigned long long *w = &h[8 * t];
+            for (int ph = 0; ph < 7; ++ph) sum[ph] += (double)(long long)(w[ph + 1] - w[ph]);
+            sum[7] += (double)(long long)(w[7] - w[0]);
+        }
+    }
+    b->free_dev(d);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(MPMC_EDEVICE, "phase profile: %s", hipGetErrorString(e));
+    const double us_per_tick = 1e3 / (double)(khz > 0 ? khz : 100000);
+    for (int ph = 0; ph < 8; ++ph) phase_us[ph] = sum[ph] / ((double)nt * nt * sweeps) * us_per_tick;
+    return MPMC_OK;
+}
+
 extern "C" int mpmc_get_info(mpmc_box bh, mpmc_info *info) {
     if (!bh || !info) return fail(MPMC_EINVAL, "NULL argument");
     Box *b = B(bh);

@@ -44,7 +44,10 @@ void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_
 struct FusedShape { uint32_t tile, threads; };
 bool fused_supported(const BoxView &v, const FusedShape &s);
 const FusedShape *fused_shapes(uint32_t *count);
-void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st);
+// stamps (NULL normally): eight realtime-clock words per tile, for the
+// phase profile
+void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st,
+                        unsigned long long *stamps = nullptr);
 // views[2 b + parity]: box b read from buffer `parity`; items: box << 20 | tile
 void launch_fused_batch(const BoxView *views, const uint32_t *items, uint32_t n_items,
                         uint32_t parity, uint32_t offset, const FusedShape &s, hipStream_t st);

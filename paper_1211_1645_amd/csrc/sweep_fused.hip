@@ -271,11 +271,18 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
     }
 }
 
+// Phase profiling: with a non-NULL `stamp` (eight words per tile), thread 0
+// records the realtime clock when the tile starts, after the region load,
+// after each colour pass, after the re-bin's class counts and at the end.
+__device__ __forceinline__ void stamp_at(unsigned long long *stamp, int tid, int k) {
+    if (stamp && tid == 0) stamp[k] = wall_clock64();
+}
+
 // The work of one tile: load, four colour passes, canonical write-back,
 // re-bin into the next sweep's grid, counts.
 template <int TILE, int THREADS, typename View>
 __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid, uint32_t I0,
-                                           uint32_t J0) {
+                                           uint32_t J0, unsigned long long *stamp) {
     constexpr int RL = Lds<TILE>::RL, R = Lds<TILE>::R, TE = Lds<TILE>::TE;
     constexpr int NL = RL * RL, NIT = (NL + THREADS - 1) / THREADS;  // loaded cells per thread
     constexpr int NE = TE * TE, NEIT = (NE + THREADS - 1) / THREADS;  // extended-block cells
@@ -288,6 +295,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     const float w = v.w;
     const float cen = (float)(v.W >> 1) * kQ;  // centring offset c
     const uint32_t gx0 = wrap_add(I0, -kHalo, M), gy0 = wrap_add(J0, -kHalo, M);
+    stamp_at(stamp, tid, 0);
 
     // ---- load the region ----------------------------------------------------
     // Counts and slots 0 and 1 are loaded together (slot 1 is read whether
@@ -340,6 +348,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         if (m > 2) L.big = 1u;
     }
     __syncthreads();
+    stamp_at(stamp, tid, 1);
 
     // Tags of the extended block, loaded now and held in registers through
     // the passes: a disk keeps its slot while the passes move it.
@@ -384,6 +393,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, tid, p, trials, accepts); break;
         }
         __syncthreads();
+        stamp_at(stamp, tid, 2 + p);
     }
 
     // ---- canonical state of the own block; wrap classes for the next grid ---
@@ -439,6 +449,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             if (f < NE) L.gcnt[f] = (uint16_t)g;
         }
         __syncthreads();
+        stamp_at(stamp, tid, 6);
 
         // ---- scatter into the next sweep's cell lists ---------------------------
         // New cell (I, J) takes the disks of old (I, J) that do not wrap, then
@@ -495,18 +506,23 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     if (ctx.big) rebin(std::integral_constant<int, 4>{});
     else rebin(std::integral_constant<int, 2>{});
     count_trials((DevScalars *)v.dev, trials, accepts);
+    if (stamp) {
+        __syncthreads();
+        stamp_at(stamp, tid, 7);
+    }
 }
 
 template <int TILE, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint32_t nty,
-                                                   uint32_t per_xcd) {
+                                                   uint32_t per_xcd, unsigned long long *stamps) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
     // Consecutive workgroups go to different XCDs; give each XCD a
     // contiguous run of tiles so that shared halo cells meet in its L2.
     const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
     if (tile >= ntx * nty) return;
-    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE);
+    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE,
+                              stamps ? stamps + 8 * (size_t)tile : nullptr);
 }
 
 // Persistent form for a batch of independent boxes: workgroups stride over
@@ -547,14 +563,15 @@ __global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restri
         v.seed_hi = src.seed_hi;
         v.offset = offset;
         const uint32_t ntx = (v.M + TILE - 1) / TILE;
-        fused_tile<TILE, THREADS>(L, v, opaque_tid(), (tile % ntx) * TILE, (tile / ntx) * TILE);
+        fused_tile<TILE, THREADS>(L, v, opaque_tid(), (tile % ntx) * TILE, (tile / ntx) * TILE,
+                                  nullptr);
         __syncthreads();
     }
 }
 
 namespace {
 template <int TILE, int THREADS>
-void launch_t(const BoxView &v, hipStream_t st) {
+void launch_t(const BoxView &v, hipStream_t st, unsigned long long *stamps) {
     const uint32_t ntx = (v.M + TILE - 1) / TILE, nty = ntx;
     const uint32_t nt = ntx * nty, per_xcd = (nt + 7) / 8;
     const size_t lds = sizeof(Lds<TILE>);
@@ -564,7 +581,7 @@ void launch_t(const BoxView &v, hipStream_t st) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    k_fused<TILE, THREADS><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd);
+    k_fused<TILE, THREADS><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd, stamps);
 }
 
 template <int TILE, int THREADS>
@@ -590,7 +607,7 @@ int occupancy_t() {
 
 struct Entry {
     uint32_t tile, threads;
-    void (*fn)(const BoxView &, hipStream_t);
+    void (*fn)(const BoxView &, hipStream_t, unsigned long long *);
     void (*batch)(const BoxView *, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                   hipStream_t);
     int (*occ)();
@@ -638,10 +655,11 @@ void launch_fused_batch(const BoxView *views, const uint32_t *items, uint32_t n_
         }
 }
 
-void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st) {
+void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st,
+                        unsigned long long *stamps) {
     for (const Entry &e : kShapes)
         if (e.tile == s.tile && e.threads == s.threads) {
-            e.fn(v, st);
+            e.fn(v, st, stamps);
             return;
         }
 }

@@ -93,6 +93,7 @@ _SIGS = {
                  C.POINTER(C.c_double)],
     "mpmc_set_schedule": [_P, C.c_uint32, C.c_uint32, C.c_uint32],
     "mpmc_set_graphs": [_P, C.c_uint32],
+    "mpmc_profile_phases": [_P, C.c_uint32, _P],
     "mpmc_batch_create": [C.POINTER(C.c_void_p), C.c_uint32, _P, _P, _P, C.POINTER(Params)],
     "mpmc_batch_free": [_P],
     "mpmc_batch_sweep": [_P, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
@@ -269,6 +270,16 @@ class Box:
 
     def set_graphs(self, sweeps_per_graph):
         _check(_lib.mpmc_set_graphs(self.h, sweeps_per_graph))
+
+    PHASES = ("load", "pass1", "pass2", "pass3", "pass4", "rebin_classes", "rebin_scatter",
+              "tile")
+
+    def profile_phases(self, sweeps=20):
+        """Mean microseconds per tile of each phase of the fused sweep
+        kernel (the box advances by `sweeps` sweeps)."""
+        out = np.zeros(8, np.float64)
+        _check(_lib.mpmc_profile_phases(self.h, sweeps, _ptr(out)))
+        return dict(zip(self.PHASES, out.tolist()))
 
     # ---- observables --------------------------------------------------------
     def accumulate_contacts(self):
