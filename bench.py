@@ -104,6 +104,8 @@ def stored_tau():
     out = {k: d.get(k) for k in keys}
     out["independent_runs"] = len(d.get("independent_runs", [])) or 1
     out["N"], out["eta"], out["source"] = 512 * 512, 0.698, "profiles/psi6_tau_512sq_eta0698.json"
+    out["provenance"] = ("stored: measured by the command above on an MI355X earlier, "
+                         "read from profiles/psi6_tau_512sq_eta0698.json; not measured in this run")
     return out
 
 
@@ -119,6 +121,8 @@ def stored_tau_bound():
                                  "abs_Psi6_mean_after_discard", "orientation_drift_deg",
                                  "command")}
     out["source"] = "profiles/psi6_tau_1024sq_eta0716.json"
+    out["provenance"] = ("stored: measured by the command above on an MI355X earlier, "
+                         "read from profiles/psi6_tau_1024sq_eta0716.json; not measured in this run")
     return out
 
 
@@ -134,6 +138,8 @@ def stored_pressure():
                                  "displacements_per_run", "command")}
     out["N"], out["eta"], out["replicas"] = 256 * 256, 0.698, d["config"]["replicas"]
     out["source"] = "profiles/pressure_256sq_eta0698.json"
+    out["provenance"] = ("stored: measured by the command above on an MI355X earlier, "
+                         "read from profiles/pressure_256sq_eta0698.json; not measured in this run")
     return out
 
 
@@ -152,62 +158,214 @@ def copy_calibration(nbytes=512 << 20, reps=3):
 LEARN_STEP_FACTOR = 3
 
 
-def learned_comparison(seed, minutes_budget=0.5):
-    """Learned proposal against the uniform one on the same w >= 3 cell grid
-    at N = 1024^2, eta = 0.716: train on accepted moves of an N = 256^2 box,
-    then measure acceptance, mean squared displacement per trial and per
-    second."""
-    import numpy as np
+TC_SIDE, TC_ETA = 128, 0.66          # Psi_6 decorrelation comparison box
+
+
+def train_learner(side, eta, seed, step_factor=LEARN_STEP_FACTOR):
+    """A learned proposal for the box N = side^2 at eta on the w >= 3 grid:
+    accepted plain moves at step_factor times the tuned step (so that the
+    network learns the larger moves a neighbourhood allows), 3000 Adam
+    steps of 8192.  Returns (learner, facts)."""
     import torch
     import paper_1211_1645_amd.mpmc as mp
-    Q = 2.0 ** -22
-    tb = mp.Box(65536, ETA, seed=seed + 1, step_m=40, cell_min=3.0, schedule="simple")
+    tb = mp.Box(side * side, eta, seed=seed + 1, step_m=40, cell_min=3.0, schedule="simple")
     m_train, _ = tune_step(tb)
-    tb.sweep(200)
-    # the moves learned from are the plain sampler's accepted moves at three
-    # times its tuned step: the network then proposes the larger moves that
-    # the neighbourhood allows
-    tb.set_step(min(255, LEARN_STEP_FACTOR * m_train))
+    tb.sweep(2000)
+    tb.set_step(min(255, step_factor * m_train))
     L = mp.Learner(seed=seed + 2, capacity=1 << 22)
-    n = L.collect(tb, 150)
+    n = 0
+    while n < (1 << 21):
+        n = L.collect(tb, 100)
     t0 = time.perf_counter()
     loss0 = L.train(1, batch=8192, lr=2e-3)
     loss = L.train(3000, batch=8192, lr=1e-3)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    progress("learned proposal trained on %d moves in %.1f s" % (n, train_s))
-    out = {"train": {"moves": n, "step_m": min(255, LEARN_STEP_FACTOR * m_train),
-                     "tuned_step_m": m_train, "steps": 3001, "batch": 8192, "loss_first": loss0,
-                     "loss_last": loss, "seconds": train_s}}
-    for mode in ("uniform", "learned"):
-        b = mp.Box(N_DISKS, ETA, seed=seed + 3, step_m=40, cell_min=3.0, schedule="simple")
-        m, _ = tune_step(b)
-        b.sweep(50)
-        run = (lambda k: b.sweep(k)) if mode == "uniform" else \
-            (lambda k: mp.sweep_learned(b, L, k, eps=0.1))
-        run(2)
-        X0, Y0 = b.positions_q()
-        i0 = b.info()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        run(20)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        X1, Y1 = b.positions_q()
-        i1 = b.info()
-        Lq = i1["W"] * i1["M"]
-        dx = (X1 - X0) % Lq
-        dx = np.where(2 * dx > Lq, dx - Lq, dx) * Q
-        dy = (Y1 - Y0) % Lq
-        dy = np.where(2 * dy > Lq, dy - Lq, dy) * Q
-        tr = i1["trials"] - i0["trials"]
-        msd = float(np.mean(dx * dx + dy * dy))
-        out[mode] = {"step_m": m, "acceptance": (i1["accepts"] - i0["accepts"]) / tr,
-                     "trial_moves_per_s": tr / dt, "sweep_us": dt / 20 * 1e6,
-                     "msd_per_trial_per_disk": msd * b.N / tr, "msd_per_s": msd / dt}
-    out["gain_msd_per_trial"] = out["learned"]["msd_per_trial_per_disk"] / \
-        out["uniform"]["msd_per_trial_per_disk"]
-    out["gain_msd_per_s"] = out["learned"]["msd_per_s"] / out["uniform"]["msd_per_s"]
+    return L, {"moves": n, "step_m": min(255, step_factor * m_train), "tuned_step_m": m_train,
+               "adam_steps": 3001, "batch": 8192, "loss_first": loss0, "loss_last": loss,
+               "seconds": time.perf_counter() - t0}
+
+
+def psi6_runs(make_box, advance, runs, equil, sweeps, every, label):
+    """`runs` independent boxes, each on a stream of its own so that the
+    small boxes run side by side: `equil` sweeps, then `sweeps` more with
+    Psi_6 every `every`.  Returns (series per run, elapsed seconds of the
+    measured part, trials per disk and sweep)."""
+    import numpy as np
+    import torch
+    streams = [torch.cuda.Stream() for _ in range(runs)]
+    boxes = []
+    for r in range(runs):
+        with torch.cuda.stream(streams[r]):
+            boxes.append(make_box(r, streams[r].cuda_stream))
+    for b in boxes:
+        advance(b, equil)
+    torch.cuda.synchronize()
+    i0 = [b.info() for b in boxes]
+    n = sweeps // every
+    series = np.zeros((runs, n), np.complex128)
+    t0 = time.perf_counter()
+    last = t0
+    for k in range(n):
+        for b in boxes:
+            advance(b, every)
+        for r, b in enumerate(boxes):
+            series[r, k] = b.psi6()
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            progress("%s: %d of %d sweeps" % (label, (k + 1) * every, sweeps))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    i1 = [b.info() for b in boxes]
+    disp = sum(a["trials"] - z["trials"] for a, z in zip(i1, i0)) / (runs * n * every * boxes[0].N)
+    return series, elapsed, disp
+
+
+def efold(series, maxlag):
+    """First lag at which C(dt) of Eq. (9) falls below 1/e (NaN if never)."""
+    import numpy as np
+    import paper_1211_1645_amd.mpmc as mp
+    Cv = mp.acf(series, maxlag)
+    below = np.nonzero(Cv < math.exp(-1.0))[0]
+    return float(below[0]) if len(below) else float("nan")
+
+
+def phases_bench(args):
+    """Per-phase profile of the sweep kernel on the benchmark's box: device
+    clock stamps at the phase boundaries of every tile (mpmc_profile_phases),
+    mean microseconds per tile."""
+    import paper_1211_1645_amd.mpmc as mp
+    box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular")
+    step_m, _ = tune_step(box)
+    box.sweep(200)
+    info = box.info()
+    ph = box.profile_phases(50)
+    print(json.dumps({"workload": "phase profile of the sweep kernel, N=1024^2 eta=0.716, "
+                                  "step m=%d, tile %d, 50 sweeps" % (step_m, info["tile"]),
+                      "tile": info["tile"], "us_per_tile": ph,
+                      "share": {k: v / ph["tile"] for k, v in ph.items() if k != "tile"},
+                      "kernel_digest": kernel_source_digest()}))
+
+
+def tau_compare_bench(args):
+    """Psi_6 decorrelation of the learned proposal against the plain one
+    (Sec. III, Eq. (9); Table II's units): N = side^2 at eta, three
+    independent runs per sampler, each about 100 plain correlation times
+    long after equilibration.  Samplers: plain on the w >= 3 grid (the
+    learned proposal's grid), plain on its own w >= 2 grid (the fused
+    kernel), learned on the w >= 3 grid.  tau is the e-folding lag of
+    C(dt); the rate is sweeps per second of the runs side by side divided by
+    tau in sweeps."""
+    import numpy as np
+    import paper_1211_1645_amd.mpmc as mp
+    side, eta, R = args.tc_side, args.tc_eta, 3
+    L, train = train_learner(side, eta, args.seed)
+    progress("tau-compare: learned proposal trained (%d moves)" % train["moves"])
+    probe = mp.Box(side * side, eta, seed=args.seed, step_m=40, cell_min=3.0, schedule="simple")
+    m3, _ = tune_step(probe)
+    probe2 = mp.Box(side * side, eta, seed=args.seed, step_m=40)
+    m2, _ = tune_step(probe2)
+    every, sweeps, equil = args.tc_every, args.tc_sweeps, args.tc_equil
+    samplers = {
+        "plain_w3": (lambda r, st: mp.Box(side * side, eta, seed=args.seed + 10 + r, step_m=m3,
+                                          cell_min=3.0, schedule="simple", stream=st),
+                     lambda b, k: b.sweep(k)),
+        "plain_w2_fused": (lambda r, st: mp.Box(side * side, eta, seed=args.seed + 20 + r,
+                                                step_m=m2, stream=st),
+                           lambda b, k: b.sweep(k)),
+        "learned_w3": (lambda r, st: mp.Box(side * side, eta, seed=args.seed + 30 + r, step_m=m3,
+                                            cell_min=3.0, schedule="simple", stream=st),
+                       None),
+    }
+    out = {}
+    for name, (make, adv) in samplers.items():
+        if adv is None:
+            # equilibrated by the plain sweep, then measured with the learned
+            # proposal
+            def make_eq(r, st, make=make):
+                b = make(r, st)
+                b.sweep(equil)
+                return b
+            series, el, disp = psi6_runs(make_eq, lambda b, k: mp.sweep_learned(b, L, k, eps=args.tc_eps),
+                                         R, 0, sweeps, every, name)
+        else:
+            series, el, disp = psi6_runs(make, adv, R, equil, sweeps, every, name)
+        taus = np.array([efold(x, len(x) // 4) * every for x in series])
+        rate = R * sweeps / el
+        tm, tse = float(np.mean(taus)), float(np.std(taus, ddof=1) / math.sqrt(R))
+        out[name] = {"tau_sweeps_runs": taus.tolist(), "tau_sweeps": tm, "tau_sweeps_se": tse,
+                     "tau_trials_per_disk": tm * disp, "tau_trials_per_disk_se": tse * disp,
+                     "trials_per_disk_per_sweep": disp, "sweeps_per_s_all_runs": rate,
+                     "decorrelations_per_s": rate / tm,
+                     "decorrelations_per_s_se": rate / tm * tse / tm,
+                     "abs_Psi6_mean": float(np.abs(series).mean()),
+                     "run_length_in_tau": sweeps / tm}
+        progress("tau-compare: %s tau = %.0f +- %.0f sweeps, %.3g decorrelations/s" %
+                 (name, tm, tse, rate / tm))
+    base = out["plain_w3"]
+    lr = out["learned_w3"]
+    line = {
+        "metric": "psi6-decorrelations/s, learned against plain, %d^2 disks eta=%.2f" % (side, eta),
+        "value": lr["decorrelations_per_s"], "unit": "decorrelations/s",
+        "n_gpus": 1, "steps": sweeps // every, "warmup": equil,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (sampler), f64 (proposal law)",
+        "data": "synthetic (triangular-lattice starts, Philox4x32-10 seeds %d..)" % args.seed,
+        "config": {"workload": "Psi6 decorrelation, N=%d^2 eta=%.2f, %d runs per sampler side "
+                               "by side, %d sweeps each after %d, Psi6 every %d; learned eps=%.2f"
+                               % (side, eta, R, sweeps, equil, every, args.tc_eps),
+                   "N": side * side, "eta": eta, "step_m_w3": m3, "step_m_w2": m2},
+        "train": train,
+        "samplers": out,
+        "gain_tau_per_sweep_vs_plain_w3": base["tau_sweeps"] / lr["tau_sweeps"],
+        "gain_tau_per_trial_vs_plain_w3": base["tau_trials_per_disk"] / lr["tau_trials_per_disk"],
+        "gain_decorrelations_per_s_vs_plain_w3": lr["decorrelations_per_s"] /
+                                                  base["decorrelations_per_s"],
+        "gain_decorrelations_per_s_vs_plain_w2_fused": lr["decorrelations_per_s"] /
+                                                        out["plain_w2_fused"]["decorrelations_per_s"],
+    }
+    print(json.dumps(line))
+
+
+def stored_tau_compare():
+    """The learned-against-plain decorrelation comparison from its committed
+    summary (`--workload tau-compare`), or None."""
+    path = os.path.join(ROOT, "profiles", "psi6_tau_learned_vs_plain_128sq_eta066.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    out = {k: d.get(k) for k in ("gain_tau_per_sweep_vs_plain_w3", "gain_tau_per_trial_vs_plain_w3",
+                                 "gain_decorrelations_per_s_vs_plain_w3",
+                                 "gain_decorrelations_per_s_vs_plain_w2_fused", "command")}
+    out["decorrelations_per_s"] = {k: [v["decorrelations_per_s"], v["decorrelations_per_s_se"]]
+                                   for k, v in d["samplers"].items()}
+    out["tau_sweeps"] = {k: [v["tau_sweeps"], v["tau_sweeps_se"]] for k, v in d["samplers"].items()}
+    out["provenance"] = ("stored: measured by the command above on an MI355X earlier, read from "
+                         "profiles/psi6_tau_learned_vs_plain_128sq_eta066.json; not measured in "
+                         "this run")
+    return out
+
+
+def learned_speed(seed):
+    """Sweep cost of the learned proposal against the plain one, live: at the
+    decorrelation-comparison box and at N = 1024^2 (w >= 3 grid, simple
+    schedule for plain), microseconds per sweep."""
+    import torch
+    import paper_1211_1645_amd.mpmc as mp
+    L = mp.Learner(seed=seed + 2, capacity=16)
+    out = {}
+    for side in (TC_SIDE, 1024):
+        b = mp.Box(side * side, TC_ETA if side == TC_SIDE else ETA, seed=seed + 3, step_m=40,
+                   cell_min=3.0, schedule="simple")
+        res = {}
+        for mode, run in (("plain_w3", lambda k: b.sweep(k)),
+                          ("learned_w3", lambda k: mp.sweep_learned(b, L, k, eps=0.1))):
+            run(4)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            run(40)
+            torch.cuda.synchronize()
+            res[mode + "_sweep_us"] = (time.perf_counter() - t) / 40 * 1e6
+        out["N=%d^2" % side] = res
     return out
 
 
@@ -223,7 +381,7 @@ ALU_OPS_RHO_TERM = 23.0
 
 
 def positional_bench(args):
-    """Positional order (Sec. IV.D) on an equilibrating N = 1024^2 box at
+    """Positional order (Sec. IV.C, IV.D) on an equilibrating N = 1024^2 box at
     eta = 0.716: the structure-factor scan for q0, chi_j, and C_q0(r) out to
     r = 100 sigma."""
     import math
@@ -764,13 +922,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workload",
-                    choices=("sweep", "positional", "tau", "scale", "batch", "pressure", "eos"),
+                    choices=("sweep", "positional", "tau", "scale", "batch", "pressure", "eos",
+                             "tau-compare", "phases"),
                     default="sweep",
                     help="sweep: the sampler (default); positional: S(q), chi_j, C_q0(r); "
                          "tau: Psi6 correlation time at N=512^2, eta=0.698 (minutes); "
                          "scale: the sweep at N=4096^2; batch: 64 boxes in one launch; "
                          "pressure: P* at N=256^2, eta=0.698 over replicas (minutes); "
-                         "eos: P*(eta) and its loop at N=128^2 and 256^2 (minutes)")
+                         "eos: P*(eta) and its loop at N=128^2 and 256^2 (minutes); "
+                         "tau-compare: Psi6 decorrelation, learned against plain (minutes); "
+                         "phases: per-phase profile of the sweep kernel")
     ap.add_argument("--tau-side", type=int, default=512, help="tau run: N = side^2")
     ap.add_argument("--tau-eta", type=float, default=TAU_ETA)
     ap.add_argument("--tau-sweeps", type=int, default=20000000)
@@ -782,6 +943,12 @@ def main():
     ap.add_argument("--p-sweeps", type=int, default=4000000)
     ap.add_argument("--p-block", type=int, default=250000)
     ap.add_argument("--p-sample", type=int, default=100)
+    ap.add_argument("--tc-side", type=int, default=TC_SIDE)
+    ap.add_argument("--tc-eta", type=float, default=TC_ETA)
+    ap.add_argument("--tc-sweeps", type=int, default=240000)
+    ap.add_argument("--tc-equil", type=int, default=20000)
+    ap.add_argument("--tc-every", type=int, default=40)
+    ap.add_argument("--tc-eps", type=float, default=0.1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -814,6 +981,12 @@ def main():
         return
     if args.workload == "eos":
         eos_bench(args)
+        return
+    if args.workload == "tau-compare":
+        tau_compare_bench(args)
+        return
+    if args.workload == "phases":
+        phases_bench(args)
         return
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -909,7 +1082,8 @@ def main():
                      "kernel_digest": kernel_source_digest()},
     }
     if not args.no_learned:
-        line["learned_vs_uniform"] = learned_comparison(args.seed)
+        line["learned_vs_uniform"] = {"sweep_cost_live": learned_speed(args.seed),
+                                      "psi6_decorrelation": stored_tau_compare()}
         progress("learned comparison done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(0, args.seed, step_m)

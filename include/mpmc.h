@@ -159,14 +159,15 @@ int mpmc_contact_hist_subset(mpmc_box b, const uint8_t *sel, int64_t *counts);
 int mpmc_psi6_field(mpmc_box b, float *re, float *im, float *field_re, float *field_im,
                     double *Psi_re, double *Psi_im, int on_device);
 
-/* Positional order, Sec. IV.D.  Wave vectors are those the periodic box
+/* Positional order, Sec. IV.C (S(q), q0, chi_j: Eqs. (10), (11)) and Sec. IV.D
+ * (C_q0(r): Eq. (12)).  Wave vectors are those the periodic box
  * allows, q = (2 pi / L_eff)(h, k) with integers |h|, |k| < 4096 and
  * L_eff = M w.  Positions are the exact absolute ones in q units; each phase
  * (h X + k Y) / (M W) is formed in fp64 (structure factor) or reduced
  * exactly in integers (chi) before its sine and cosine. */
 
 /* Structure factor S(q) = |sum_n exp(i q.x_n)|^2 / N (the double sum over
- * n, m of Sec. IV.D) at nq wave vectors: hk holds (h, k) pairs, S receives
+ * n, m of Sec. IV.C) at nq wave vectors: hk holds (h, k) pairs, S receives
  * nq values (host arrays).  Each term exp(i q.x) is an fp32 root of unity
  * from a 256-entry table, chosen by the fp64 phase, rotated by the residual
  * angle in fp32, and summed in fp64: every term carries an absolute error
@@ -201,7 +202,7 @@ int mpmc_find_q0(mpmc_box b, double q_lo, double q_hi, double theta0, double dth
  * by tag into re/im (N floats each, phase reduced exactly in integers and
  * evaluated in fp64); field_re/field_im: per cell of the current grid
  * (M*M floats, cell i + M j) the mean chi_j over its 3 x 3 block, the field
- * chi(x) drawn in Sec. IV.D.  Device pointers when on_device != 0, else
+ * chi(x) drawn in Sec. IV.C.  Device pointers when on_device != 0, else
  * host; any output may be NULL. */
 int mpmc_chi_field(mpmc_box b, int32_t h, int32_t k, float *re, float *im, float *field_re,
                    float *field_im, int on_device);
@@ -439,6 +440,15 @@ int mpmc_learned_features(mpmc_box b, const uint32_t *tags, uint32_t n, float *F
  * uniform fallback); counts as mpmc_sweep. */
 int mpmc_sweep_learned(mpmc_box b, mpmc_learner l, uint64_t k, float eps, uint64_t *trials,
                        uint64_t *accepts);
+
+/* Phase profile of the learned colour pass: runs `sweeps` learned sweeps
+ * (the chain advances as with mpmc_sweep_learned), lane 0 of every wave
+ * recording the device realtime clock, and returns in phase_us[9] the mean
+ * microseconds per wave and pass of: start-up (weights, neighbourhood,
+ * random words), features at x, network at x, the draw and P(D), the
+ * overlap test, features at x', network at x', the acceptance, and the
+ * count.  Allocates a stamp buffer for the call. */
+int mpmc_profile_learned(mpmc_box b, mpmc_learner l, uint32_t sweeps, float eps, double *phase_us);
 
 /* The proposal as a law on the q lattice.  A trial proposes an integer
  * displacement D = (Dx, Dy) (delta = D q) with probability

@@ -8,7 +8,10 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "liborc.so")
+# ORC_SANITIZE=1 builds and loads a copy instrumented with AddressSanitizer
+# and UndefinedBehaviorSanitizer (run Python with libasan preloaded)
+SANITIZE = os.environ.get("ORC_SANITIZE") == "1"
+LIB = os.path.join(HERE, "liborc_san.so" if SANITIZE else "liborc.so")
 
 
 def build(force: bool = False) -> str:
@@ -20,6 +23,9 @@ def build(force: bool = False) -> str:
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-D_GNU_SOURCE",
            src, "-o", tmp, "-lm"]
+    if SANITIZE:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-fno-omit-frame-pointer", "-g"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

@@ -480,9 +480,9 @@ uint64_t orc_count_overlaps(const orc_box *b) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Positional order, Sec. IV.D: the structure factor, chi_j, and the
- * positional correlation function C_q(r) averaged over pairs in a window of
- * half-width sigma around r. */
+/* Positional order: the structure factor and chi_j (Sec. IV.C, Eqs. (10),
+ * (11)), and the positional correlation function C_q(r) averaged over pairs
+ * in a window of half-width sigma around r (Sec. IV.D, Eq. (12)). */
 
 void orc_structure_factor(const orc_box *b, const int32_t *hk, uint32_t nq, double *S) {
     int64_t *X, *Y;

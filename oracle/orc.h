@@ -91,7 +91,7 @@ void orc_psi6_field(const orc_box *b, const double *re, const double *im, double
                     double *fim);
 
 /* C(dt) of Eq. (9), dt = 0..maxlag, from a complex series of length n. */
-/* Positional order (Sec. IV.D).  Structure factor
+/* Positional order (Sec. IV.C).  Structure factor
  * S(q) = |sum_n exp(i q.x_n)|^2 / N at the wave vectors the periodic box
  * allows, q = (2 pi / L_eff)(h, k); the phase (h X + k Y) mod Lq is reduced
  * exactly in integers (X, Y absolute positions in q units).  hk holds nq
@@ -101,7 +101,8 @@ void orc_structure_factor(const orc_box *b, const int32_t *hk, uint32_t nq, doub
 /* chi_j = exp(i q0.x_j) with q0 = (2 pi / L_eff)(h, k), by tag. */
 void orc_chi(const orc_box *b, int32_t h, int32_t k, double *re, double *im);
 
-/* Positional correlation C_q(r) = <exp(i q.(x_n - x_m))> over the unordered
+/* Positional correlation (Sec. IV.D, Eq. (12))
+ * C_q(r) = <exp(i q.(x_n - x_m))> over the unordered
  * pairs with minimum-image separation |x_n - x_m| in [r - 1, r + 1] (sigma = 1),
  * at r_b = b dr, b = 0..B-1.  Adds sum cos(q.d) to num[b] and the pair count
  * to cnt[b] (the sine parts cancel between (n, m) and (m, n)).  dr must be a

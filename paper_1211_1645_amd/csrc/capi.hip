@@ -473,6 +473,7 @@ extern "C" int mpmc_default_params(mpmc_params *p) {
 extern "C" int mpmc_init_box(mpmc_box *out, uint32_t N, double eta, uint64_t seed,
                              const mpmc_params *p) {
     if (!out) return fail(MPMC_EINVAL, "out is NULL");
+    *out = nullptr;
     Box *b = nullptr;
     int rc = create_box(&b, N, eta, seed, p);
     if (rc) return rc;

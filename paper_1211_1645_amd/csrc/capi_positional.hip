@@ -1,6 +1,7 @@
-// capi_positional.hip — C ABI of the positional order (Sec. IV.D): the
+// capi_positional.hip — C ABI of the positional order: the
 // structure factor at the wave vectors of the periodic box, the search for
-// the first diffraction peak q0, chi_j and its field, and C_q(r).
+// the first diffraction peak q0, chi_j and its field (Sec. IV.C), and C_q(r)
+// (Sec. IV.D).
 #include <math.h>
 
 #include <mutex>

@@ -392,23 +392,27 @@ __device__ inline bool lattice_draw(const Mix &g, const Words &A, const Words &B
         Dy = (int)m * (2 * (int)(A.w2 >> 18) + 1 - 16384);
         return true;
     }
+    // component: the first c with uc below the cumulative weight (3 if none);
+    // its parameters are carried along by selects
     const double uc = u53(B.w0, B.w1);
-    int k = 3;
-    double cum = 0.0;
+    bool chosen = false;
+    double cum = 0.0, mx = g.mx[3], my = g.my[3];
+    float ax = g.ax[3], ay = g.ay[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         cum += g.pi[c];
-        if (k == 3 && uc < cum) k = c;
+        const bool take = !chosen && uc < cum;
+        mx = take ? g.mx[c] : mx;
+        my = take ? g.my[c] : my;
+        ax = take ? g.ax[c] : ax;
+        ay = take ? g.ay[c] : ay;
+        chosen = chosen || take;
     }
     const double u1 = (double)((((uint64_t)C.w0 << 21) | (C.w1 >> 11)) + 1) * 0x1p-53;
     const double u2 = u53(C.w2, C.w3);
     const double r = sqrt(-2.0 * log(u1));
     double sn, cs;
     sincos(6.283185307179586 * u2, &sn, &cs);
-    const double mx = k == 0 ? g.mx[0] : k == 1 ? g.mx[1] : k == 2 ? g.mx[2] : g.mx[3];
-    const double my = k == 0 ? g.my[0] : k == 1 ? g.my[1] : k == 2 ? g.my[2] : g.my[3];
-    const float ax = k == 0 ? g.ax[0] : k == 1 ? g.ax[1] : k == 2 ? g.ax[2] : g.ax[3];
-    const float ay = k == 0 ? g.ay[0] : k == 1 ? g.ay[1] : k == 2 ? g.ay[2] : g.ay[3];
     const double tx = (mx + (exp((double)ax) * r) * cs) * 4194304.0;
     const double ty = (my + (exp((double)ay) * r) * sn) * 4194304.0;
     if (!(fabs(tx) < 4194303.5 && fabs(ty) < 4194303.5)) return false;
@@ -422,10 +426,13 @@ __device__ inline bool lattice_draw(const Mix &g, const Words &A, const Words &B
 // cells are distinct and the own cell is k = 4, k = 3 (dj + 1) + di + 1):
 // the nine counts (3 bits each) and slots 0 and 1 are loaded together, one
 // round trip; slots 2 and 3 are read from the lists where a count asks.
+constexpr int kExtra = 8;  // slots >= 2 of a 3 x 3 block staged in LDS per lane
 struct Nbhd {
     uint32_t m;           // count of cell k in bits 3k..3k+2
     float x[9][2], y[9][2];
     uint32_t ci, cj, M;
+    const float2 *ex;     // slots >= 2 in cell order, the first kExtra of them
+                          // (NULL: read from the lists)
 };
 
 __device__ inline uint32_t nbhd_cell(const Nbhd &N, int k) {
@@ -440,6 +447,7 @@ __device__ inline void load_nbhd(const uint8_t *cnt, const float *px, const floa
     N.cj = cj;
     N.M = M;
     N.m = 0;
+    N.ex = nullptr;
     const uint32_t NC = M * M;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -452,6 +460,23 @@ __device__ inline void load_nbhd(const uint8_t *cnt, const float *px, const floa
     }
 }
 
+// Copies slots 2.. of the nine cells (in cell order, at most kExtra) into
+// this lane's LDS area `ex` and points N at it: the neighbourhood is then
+// read from registers and LDS only.
+__device__ inline void stage_extras(Nbhd &N, const float *px, const float *py, float2 *ex) {
+    const uint32_t NC = N.M * N.M;
+    int e = 0;
+#pragma unroll 1
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t m = (N.m >> (3 * k)) & 7u;
+        if (m <= 2) continue;
+        const uint32_t nb = nbhd_cell(N, k);
+        for (uint32_t s = 2; s < m && e < kExtra; ++s, ++e)
+            ex[e] = make_float2(px[slot_at(nb, s, NC)], py[slot_at(nb, s, NC)]);
+    }
+    N.ex = ex;
+}
+
 // Calls f(dx, dy) for every disk of the block but slot `self` of the own
 // cell, in the order of cells k, then slots, with (dx, dy) its separation
 // from the point (x, y) of the own cell (each cell's offset c w added last).
@@ -459,6 +484,7 @@ template <class F>
 __device__ inline void for_each_other(const Nbhd &N, const float *px, const float *py, float w,
                                       uint32_t self, float x, float y, F &&f) {
     const uint32_t NC = N.M * N.M;
+    int eb = 0;  // staged entries of the cells before k
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const float cwx = (float)(k % 3 - 1) * w, cwy = (float)(k / 3 - 1) * w;
@@ -466,11 +492,21 @@ __device__ inline void for_each_other(const Nbhd &N, const float *px, const floa
 #pragma unroll
         for (uint32_t s = 0; s < 2; ++s)
             if (s < m && !(k == 4 && s == self)) f((N.x[k][s] - x) + cwx, (N.y[k][s] - y) + cwy);
-        if (m > 2) {  // rare: slots 2 and 3 from the lists
-            const uint32_t nb = nbhd_cell(N, k);
-            for (uint32_t s = 2; s < m; ++s)
-                if (!(k == 4 && s == self))
-                    f((px[slot_at(nb, s, NC)] - x) + cwx, (py[slot_at(nb, s, NC)] - y) + cwy);
+        // slots 2.. from the staged copy, beyond it (or without one) from
+        // the lists
+        for (uint32_t s = 2; s < m; ++s, ++eb) {
+            if (k == 4 && s == self) continue;
+            float xs, ys;
+            if (N.ex && eb < kExtra) {
+                const float2 e = N.ex[eb];
+                xs = e.x;
+                ys = e.y;
+            } else {
+                const uint32_t nb = nbhd_cell(N, k);
+                xs = px[slot_at(nb, s, NC)];
+                ys = py[slot_at(nb, s, NC)];
+            }
+            f((xs - x) + cwx, (ys - y) + cwy);
         }
     }
 }
@@ -548,7 +584,20 @@ struct LearnView {
     uint64_t E;                      // uniform branch: a 32-bit word below E
     double e;                        // its probability, E / 2^32
     unsigned long long *nfeat_over;  // neighbourhoods with more than 12 disks
+    unsigned long long *stamps;      // phase profile (NULL normally): kLearnStamps per wave
 };
+
+// Phase profile of the learned pass: lane 0 of each wave records the device
+// realtime clock at the start, before the features, after them, after the
+// network, after the draw, after the overlap test, after the reverse
+// features, after the reverse network, after the acceptance and at the end
+// (first trial of the cell only).
+constexpr int kLearnStamps = 10;
+__device__ __forceinline__ void learn_stamp(const LearnView &lv, int lane, uint32_t tr, int k) {
+    if (lv.stamps && lane == 0 && tr == 0)
+        lv.stamps[((size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kLearnStamps + k] =
+            wall_clock64();
+}
 
 constexpr int kLearnWaves = 4;  // waves per workgroup of the learned pass
 
@@ -559,6 +608,7 @@ struct LdsLearn {
     struct Wave {
         uint16_t X[64 * kXS];  // network input rows
         float so[64 * kSS];    // feature scratch, then the network output [64][kOS]
+        float2 ex[64 * kExtra];  // staged slots >= 2 of each lane's block
     } pw[kLearnWaves];
 };
 
@@ -592,6 +642,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     LdsLearn &L = *reinterpret_cast<LdsLearn *>(lds_raw);
     const int lane = threadIdx.x & 63;
     LdsLearn::Wave &P = L.pw[threadIdx.x >> 6];
+    learn_stamp(lv, lane, 0, 0);
     // the weights' copy overlaps the first trial's loads and random numbers:
     // the barrier that completes it comes just before the first network
     load_infer_weights(L.w, lv.W, threadIdx.x, 64 * kLearnWaves);
@@ -609,7 +660,11 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     // test and the reverse features, and it is read again for every further
     // trial of the cell
     Nbhd nbh;
-    if (valid) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
+    float2 *ex = P.ex + kExtra * lane;
+    if (valid) {
+        load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
+        stage_extras(nbh, v.x_out, v.y_out, ex);
+    }
     const uint32_t n = valid ? (nbh.m >> 12) & 7u : 0u;
     float *scr = P.so + kSS * lane;  // scratch before the MLP
     uint32_t trials = 0, accepts = 0;
@@ -634,7 +689,10 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         Words wa{0, 0, 0, 0}, wb{0, 0, 0, 0};
         uint32_t slot = 0;
         float x = 0.0f, y = 0.0f;
-        if (act && tr > 0) load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
+        if (act && tr > 0) {
+            load_nbhd(v.cnt_out, v.x_out, v.y_out, M, ci, cj, nbh);
+            stage_extras(nbh, v.x_out, v.y_out, ex);
+        }
         if (act) {
             wa = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamTrial);
             wb = draw(v.seed_lo, v.seed_hi, sweep, cell, tr, kStreamLearned);
@@ -643,6 +701,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
             y = slot == 0 ? nbh.y[4][0] : slot == 1 ? nbh.y[4][1] : v.y_out[slot_at(cell, slot, M * M)];
         }
         wave_sync();
+        learn_stamp(lv, lane, tr, 1);
         // sorted features into this lane's row of X
         if (act) {
             const int nf = lane_features(nbh, v.x_out, v.y_out, v.w, slot, x, y, scr,
@@ -652,9 +711,11 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
             zero_row(P.X + kXS * lane);
         }
         wave_sync();
+        learn_stamp(lv, lane, tr, 2);
         if (tr == 0) __syncthreads();  // the weights are in LDS
         float *OUT = P.so;
         mlp_infer_wave(L.w, P.X, OUT);
+        learn_stamp(lv, lane, tr, 3);
         // propose D from the lattice law and keep P(D)
         int Dx = 0, Dy = 0;
         bool drawn = false;
@@ -667,6 +728,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
             drawn = lattice_draw(g, wa, wb, wc, v.step_m, lv.E, Dx, Dy);
             if (drawn) pf = lattice_p(g, Dx, Dy, v.step_m, lv.e);
         }
+        learn_stamp(lv, lane, tr, 4);
         // geometry in q units: exact
         const int U = (int)(x * 4194304.0f) + Dx, V = (int)(y * 4194304.0f) + Dy;
         bool ok = act && drawn && U >= 0 && U < (int)v.W && V >= 0 && V < (int)v.W;
@@ -676,13 +738,16 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
                            [&](float ddx, float ddy) { ok = ok && !overlap_f32(ddx, ddy); });
         // reverse law at x' (every lane takes part in the wave GEMMs)
         wave_sync();
+        learn_stamp(lv, lane, tr, 5);
         if (ok) {
             lane_features(nbh, v.x_out, v.y_out, v.w, slot, xn, yn, scr, P.X + kXS * lane, nullptr);
         } else {
             zero_row(P.X + kXS * lane);
         }
         wave_sync();
+        learn_stamp(lv, lane, tr, 6);
         mlp_infer_wave(L.w, P.X, OUT);
+        learn_stamp(lv, lane, tr, 7);
         if (act) ++trials;
         if (ok) {
             const Mix gr = mix_from(OUT + kOS * lane);
@@ -695,8 +760,10 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
             }
         }
         wave_sync();
+        learn_stamp(lv, lane, tr, 8);
     }
     count_trials(v.dev, trials, accepts);
+    learn_stamp(lv, lane, 0, 9);
 }
 
 // ---------------------------------------------------------------------------
@@ -1367,6 +1434,50 @@ extern "C" int mpmc_learned_features(mpmc_box bh, const uint32_t *tags, uint32_t
     return MPMC_OK;
 }
 
+// k learned sweeps of box b: four colour passes, the re-bin and the counter
+// update per sweep.  With `stamps` (room for the waves of one pass) each
+// sweep is synchronised and the phase durations of every wave of every pass
+// are added to phase_ticks[kLearnStamps - 1].
+static int learned_sweeps(Box *b, Learner *l, uint64_t k, float eps, unsigned long long *stamps,
+                          double *phase_ticks) {
+    const size_t lds = sizeof(LdsLearn);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_pass_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        attr = true;
+    }
+    const uint64_t E = branch_threshold(eps);
+    const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
+    constexpr uint32_t nt = 64 * kLearnWaves;
+    const uint32_t grid = (na + nt - 1) / nt, waves = grid * kLearnWaves;
+    std::vector<unsigned long long> h(stamps ? (size_t)waves * kLearnStamps : 0);
+    for (uint64_t s = 0; s < k; ++s) {
+        BoxView v = b->view(b->cur);
+        const BoxView pv = in_place(v);
+        for (uint32_t p = 0; p < 4; ++p) {
+            LearnView lv{l->W, E, ldexp((double)E, -32), l->over, stamps};
+            k_pass_learned<<<grid, nt, lds, b->stream>>>(pv, p, lv);
+            if (stamps) {
+                HIPCHK(hipMemcpyAsync(h.data(), stamps, h.size() * 8, hipMemcpyDeviceToHost, b->stream));
+                HIPCHK(hipStreamSynchronize(b->stream));
+                for (uint32_t w = 0; w < waves; ++w)
+                    for (int ph = 0; ph + 1 < kLearnStamps; ++ph)
+                        phase_ticks[ph] += (double)(long long)(h[(size_t)w * kLearnStamps + ph + 1] -
+                                                               h[(size_t)w * kLearnStamps + ph]);
+            }
+        }
+        v.offset = 1;  // binned for the next sweep
+        launch_rebin(v, b->stream);
+        launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
+                       1, b->stream);
+        HIPCHK(hipGetLastError());
+        b->cur ^= 1;
+        b->canon_in_c = false;
+    }
+    return MPMC_OK;
+}
+
 extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, float eps,
                                   uint64_t *trials, uint64_t *accepts) {
     if (!bh || !lh) return fail(MPMC_EINVAL, "NULL argument");
@@ -1378,35 +1489,40 @@ extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, floa
     rc = b->read_scalars();
     if (rc) return rc;
     const DevScalars before = b->host;
-    const size_t lds = sizeof(LdsLearn);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_pass_learned, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        attr = true;
-    }
-    const uint64_t E = branch_threshold(eps);
-    LearnView lv{l->W, E, ldexp((double)E, -32), l->over};
-    const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
-    for (uint64_t s = 0; s < k; ++s) {
-        BoxView v = b->view(b->cur);
-        const BoxView pv = in_place(v);
-        constexpr uint32_t nt = 64 * kLearnWaves;
-        for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<(na + nt - 1) / nt, nt, lds, b->stream>>>(pv, p, lv);
-        v.offset = 1;  // binned for the next sweep
-        launch_rebin(v, b->stream);
-        launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
-                       1, b->stream);
-        HIPCHK(hipGetLastError());
-        b->cur ^= 1;
-        b->canon_in_c = false;
-    }
+    rc = learned_sweeps(b, l, k, eps, nullptr, nullptr);
+    if (rc) return rc;
     if (trials || accepts) {
         rc = b->read_scalars();
         if (rc) return rc;
         if (trials) *trials = b->host.trials - before.trials;
         if (accepts) *accepts = b->host.accepts - before.accepts;
     }
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_profile_learned(mpmc_box bh, mpmc_learner lh, uint32_t sweeps, float eps,
+                                    double *phase_us) {
+    if (!bh || !lh || !phase_us || sweeps == 0) return fail(MPMC_EINVAL, "bad arguments");
+    if (!(eps >= 0.0f) || eps > 1.0f) return fail(MPMC_EINVAL, "eps must be in [0, 1]");
+    Box *b = BX(bh);
+    Learner *l = LR(lh);
+    int rc = check_learned_box(b);
+    if (rc) return rc;
+    const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
+    const uint32_t waves = (na + 64 * kLearnWaves - 1) / (64 * kLearnWaves) * kLearnWaves;
+    unsigned long long *d = nullptr;
+    rc = b->alloc_dev((void **)&d, (size_t)waves * kLearnStamps * 8);
+    if (rc) return rc;
+    double ticks[kLearnStamps - 1] = {};
+    rc = learned_sweeps(b, l, sweeps, eps, d, ticks);
+    b->free_dev(d);
+    if (rc) return rc;
+    int dev = 0, khz = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double us_per_tick = 1e3 / (double)(khz > 0 ? khz : 100000);
+    for (int ph = 0; ph + 1 < kLearnStamps; ++ph)
+        phase_us[ph] = ticks[ph] / ((double)waves * 4 * sweeps) * us_per_tick;
     return MPMC_OK;
 }
 

@@ -1,7 +1,7 @@
-// positional.hip — positional order (Sec. IV.D): the structure factor at the
-// wave vectors the periodic box allows, chi_j = exp(i q0.x_j), and the
-// positional correlation C_q(r) averaged over pairs in a window of
-// half-width sigma around r.  One thread per cell serves the (mostly one)
+// positional.hip — positional order: the structure factor at the
+// wave vectors the periodic box allows and chi_j = exp(i q0.x_j) (Sec. IV.C,
+// Eqs. (10), (11)), and the positional correlation C_q(r) averaged over pairs
+// in a window of half-width sigma around r (Sec. IV.D, Eq. (12)).  One thread per cell serves the (mostly one)
 // disks of that cell; absolute positions come from the cell lists and the
 // accumulated shift as exact integers in q units.
 #include "mpmc_kernels.hpp"

@@ -116,6 +116,7 @@ _SIGS = {
     "mpmc_learned_features": [_P, _P, C.c_uint32, _P],
     "mpmc_sweep_learned": [_P, _P, C.c_uint64, C.c_float, C.POINTER(C.c_uint64),
                            C.POINTER(C.c_uint64)],
+    "mpmc_profile_learned": [_P, _P, C.c_uint32, C.c_float, _P],
     "mpmc_learned_propose": [_P, C.c_uint32, C.c_float, C.c_uint64, C.c_uint32, _P, _P, _P],
     "mpmc_learned_logp": [_P, _P, C.c_uint32, C.c_uint32, C.c_float, _P],
     "mpmc_learner_moves": [_P, C.c_uint64, C.c_uint64, _P, _P],
@@ -353,7 +354,7 @@ class Box:
         _check(_lib.mpmc_measure_wait(self.h, C.byref(f)))
         return bool(f.value)
 
-    # ---- positional order (Sec. IV.D) --------------------------------------
+    # ---- positional order (Sec. IV.C: S(q), q0, chi; Sec. IV.D: C_q(r)) -----
     def wave_vector(self, h, k):
         """(qx, qy) = (2 pi / L_eff)(h, k) in 1/sigma."""
         u = 2.0 * np.pi / self.info()["L_eff"]
@@ -601,6 +602,18 @@ def sweep_learned(box, learner, k=1, eps=0.1, counts=False):
     _check(load().mpmc_sweep_learned(box.h, learner.h, k, eps, C.byref(t) if counts else None,
                                      C.byref(a) if counts else None))
     return (t.value, a.value) if counts else None
+
+
+LEARN_PHASES = ("start", "features", "network", "draw", "overlap", "features_rev", "network_rev",
+                "accept", "count")
+
+
+def profile_learned(box, learner, sweeps=5, eps=0.1):
+    """Mean microseconds per wave and colour pass of each phase of the
+    learned pass (the box advances by `sweeps` learned sweeps)."""
+    out = np.zeros(9, np.float64)
+    _check(load().mpmc_profile_learned(box.h, learner.h, sweeps, eps, _ptr(out)))
+    return dict(zip(LEARN_PHASES, out.tolist()))
 
 
 def learned_propose(out, step_m, eps, seed, n):

@@ -97,41 +97,103 @@ def test_learned_sampler_exact_for_two_disks(gpu_lib):
     assert g.validate() == (0, 0)
 
 
-def test_training_reduces_loss_and_learned_matches_plain(gpu_lib, tmp_path):
-    """Collect accepted plain moves on a dense liquid, train, then compare
-    the pressure of learned and plain runs (same box size, same w >= 3
-    grid).  Each sampler is continued from four independently equilibrated
-    configurations and the error comes from the scatter between those runs:
-    the block error of one run underestimates the true one by a factor of
-    two or more at this size, because the pressure decorrelates slowly."""
-    cfg = dict(N=32 * 32, eta=0.65)
-    box = gpu_lib.Box(**cfg, seed=7, step_m=40, cell_min=3.0, schedule="simple")
-    L = gpu_lib.Learner(seed=3, capacity=1 << 18)
+def _trained_learner(gpu_lib, N, eta, seed, step_m=40):
+    """A network trained on the accepted plain moves of an equilibrated box
+    (cell_min = 3): 300 sweeps of moves, 600 Adam steps of 2048."""
+    box = gpu_lib.Box(N, eta, seed=seed, step_m=step_m, cell_min=3.0, schedule="simple")
+    box.sweep(2000)
+    L = gpu_lib.Learner(seed=3, capacity=1 << 19)
     n = L.collect(box, 300)
     assert n > 10000
     l0 = L.train(1, batch=2048, lr=1e-3)
     l1 = L.train(600, batch=2048, lr=1e-3)
-    assert l1 < l0 - 0.3, (l0, l1)
     assert L.info()["feature_overflow"] == 0
-    Ps = {"plain": [], "learned": []}
-    for seed in range(100, 104):
-        eq = gpu_lib.Box(**cfg, seed=seed, step_m=40, cell_min=3.0, schedule="simple",
-                         hist_bins=20, hist_dr=0.01, hist_block=500)
-        eq.sweep(3000)
-        start = str(tmp_path / ("equilibrated_%d.ckpt" % seed))
-        eq.save(start)
+    return L, l0, l1
+
+
+def test_training_reduces_loss(gpu_lib):
+    _, l0, l1 = _trained_learner(gpu_lib, 64 * 64, 0.716, 7)
+    assert l1 < l0 - 0.3, (l0, l1)
+
+
+def _paired(gpu_lib, L, N, eta, seeds, equil, sweeps, every, tmp_path):
+    """For each seed: a plain run from the triangular start for `equil`
+    sweeps, saved; then `sweeps` more with the plain and with the learned
+    proposal from that same state.  Every box runs on a stream of its own, so
+    the small boxes advance side by side.  Per run: P* from the contact
+    histogram, and the means of |Psi_6| (global) and of |psi_j| over disks
+    (local), sampled every `every` sweeps.  Returns {mode: [(P*, |Psi6|,
+    |psi_j|), ...]}."""
+    import torch
+    seeds = list(seeds)
+    streams = [torch.cuda.Stream() for _ in seeds]
+    starts = []
+    for seed, st in zip(seeds, streams):
+        eq = gpu_lib.Box(N, eta, seed=seed, step_m=40, cell_min=3.0, schedule="simple",
+                         hist_bins=20, hist_dr=0.01, stream=st.cuda_stream)
+        eq.sweep(equil)
+        starts.append(eq)
+    paths = []
+    for seed, eq in zip(seeds, starts):
+        paths.append(str(tmp_path / ("start_%d.ckpt" % seed)))
+        eq.save(paths[-1])
+    runs = []  # (mode, box)
+    for i, path in enumerate(paths):
         for mode in ("plain", "learned"):
-            b = gpu_lib.Box.load(start, schedule="simple")
-            for _ in range(3000):
-                if mode == "plain":
-                    b.sweep(2)
-                else:
-                    gpu_lib.sweep_learned(b, L, 2, eps=0.1)
-                b.accumulate_contacts()
-            Ps[mode].append(b.measure_pressure()["P_star"])
-            assert b.validate() == (0, 0)
-    p, q = np.array(Ps["plain"]), np.array(Ps["learned"])
-    se = math.sqrt(p.var(ddof=1) / len(p) + q.var(ddof=1) / len(q))
-    d = q.mean() - p.mean()
-    # 4 standard errors: about 1% false alarms with 6 degrees of freedom
-    assert abs(d) < 4 * se, (Ps, d, se)
+            st = torch.cuda.Stream()
+            runs.append((mode, gpu_lib.Box.load(path, schedule="simple", stream=st.cuda_stream), [], []))
+    for _ in range(sweeps // every):
+        for mode, b, _, _ in runs:
+            if mode == "plain":
+                b.sweep(every)
+            else:
+                gpu_lib.sweep_learned(b, L, every, eps=0.1)
+            b.accumulate_contacts()
+        for mode, b, glob, loc in runs:
+            psi, _, Psi = b.psi6_field()
+            glob.append(abs(Psi))
+            loc.append(float(np.abs(psi).mean()))
+    out = {"plain": [], "learned": []}
+    for mode, b, glob, loc in runs:
+        assert b.validate() == (0, 0)
+        out[mode].append((b.measure_pressure()["P_star"], float(np.mean(glob)), float(np.mean(loc))))
+    return out
+
+
+def _assert_paired_agreement(res, label):
+    """The learned run minus the plain run from the same start, over the
+    seeds: the mean difference of P*, of |Psi_6| and of |psi_j| within 3
+    standard errors of the paired differences."""
+    p, q = np.array(res["plain"]), np.array(res["learned"])
+    d = q - p
+    n = len(d)
+    for j, name in enumerate(("P*", "|Psi6|", "|psi_j|")):
+        se = d[:, j].std(ddof=1) / math.sqrt(n)
+        assert se > 0
+        assert abs(d[:, j].mean()) < 3 * se, (label, name, d[:, j].mean(), se, p[:, j], q[:, j])
+
+
+# The learned proposal is compared with the plain one where both chains can
+# be started in equilibrium: liquids whose global Psi_6 decorrelates within
+# a few thousand plain sweeps (tau about 1200 sweeps at N = 32^2, eta = 0.65
+# and 2300 at N = 128^2, eta = 0.66).  At eta = 0.716 the global order of a
+# lattice start relaxes over more than 10^6 sweeps, so two exact samplers
+# that relax at different speeds legitimately differ over any run a test can
+# afford; there the learned sweep is tied to the oracle by the bit-exact
+# fixed-mixture trajectories instead.
+def test_learned_matches_plain_liquid_16384(gpu_lib, tmp_path):
+    """N = 128^2 at eta = 0.66, eight starts equilibrated for 2.5e4 plain
+    sweeps (about 11 tau), then 2.4e4 sweeps of each sampler from the same
+    state: P*, |Psi_6| and |psi_j| agree within 3 standard errors."""
+    L, _, _ = _trained_learner(gpu_lib, 128 * 128, 0.66, 5)
+    res = _paired(gpu_lib, L, 128 * 128, 0.66, range(100, 108), 25000, 24000, 100, tmp_path)
+    _assert_paired_agreement(res, "N=128^2 eta=0.66")
+
+
+def test_learned_matches_plain_liquid_1024(gpu_lib, tmp_path):
+    """N = 32^2 at eta = 0.65: eight starts equilibrated for 10^4 sweeps,
+    then 2 10^4 sweeps of each sampler (about 16 tau): P*, |Psi_6| and
+    |psi_j| agree within 3 standard errors."""
+    L, _, _ = _trained_learner(gpu_lib, 32 * 32, 0.65, 9)
+    res = _paired(gpu_lib, L, 32 * 32, 0.65, range(200, 208), 10000, 20000, 50, tmp_path)
+    _assert_paired_agreement(res, "N=32^2 eta=0.65")

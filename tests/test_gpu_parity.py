@@ -93,7 +93,7 @@ def test_n65536_triangular_trajectory_bit_exact(gpu_lib):
     assert g.info()["schedule"] == 2
     o = OracleBox(**TRI_65536)
     done = 0
-    for k in (1, 10, 60):
+    for k in (1, 10, 60, 1000):
         g.sweep(k - done)
         o.sweep(k - done)
         done = k
@@ -240,7 +240,7 @@ def test_full_size_parity_sampled(gpu_lib):
     opsi = o.psi6(sel)
     idx = np.nonzero(sel)[0]
     assert np.abs(psi[idx] - opsi[idx]).max() < 1e-5
-    # positional order (Sec. IV.D): S at sampled wave vectors, chi sampled
+    # positional order (Sec. IV.C): S at sampled wave vectors, chi sampled
     hk = np.array([[0, 0], [1, 0], [0, 1024], [-512, 886], [511, -886], [4095, 4095]], np.int32)
     S, So = g.structure_factor(hk), o.structure_factor(hk)
     assert np.all(np.abs(S - So) <= 2e-6 * np.sqrt(cfg["N"] * So) + 1e-12 * cfg["N"] + 1e-12)

@@ -1,4 +1,4 @@
-"""Positional order (Sec. IV.D) through the C ABI against the oracle, on
+"""Positional order (Sec. IV.C, IV.D) through the C ABI against the oracle, on
 states that both sides reach by the same bit-exact trajectory.
 
 Tolerances follow from the arithmetic: the GPU evaluates each term of the

@@ -482,7 +482,7 @@ def test_adam_first_step():
 
 
 # --------------------------------------------------------------------------
-# Positional order (Sec. IV.D): S(q), chi_j and C_q(r)
+# Positional order: S(q) and chi_j (Sec. IV.C), C_q(r) (Sec. IV.D)
 def _square_lattice(n, eta):
     """n x n square lattice placed at (i + 1/2) Lq / n in q units."""
     b = OracleBox(n * n, eta, lattice=2)
