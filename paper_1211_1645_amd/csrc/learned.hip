@@ -465,15 +465,35 @@ __device__ inline void load_nbhd(const uint8_t *cnt, const float *px, const floa
 // read from registers and LDS only.
 __device__ inline void stage_extras(Nbhd &N, const float *px, const float *py, float2 *ex) {
     const uint32_t NC = N.M * N.M;
-    int e = 0;
-#pragma unroll 1
+    // entries before each cell
+    uint32_t before[9];
+    uint32_t e = 0;
+#pragma unroll
     for (int k = 0; k < 9; ++k) {
+        before[k] = e;
         const uint32_t m = (N.m >> (3 * k)) & 7u;
-        if (m <= 2) continue;
-        const uint32_t nb = nbhd_cell(N, k);
-        for (uint32_t s = 2; s < m && e < kExtra; ++s, ++e)
-            ex[e] = make_float2(px[slot_at(nb, s, NC)], py[slot_at(nb, s, NC)]);
+        e += m > 2 ? m - 2 : 0;
     }
+    // entry q is slot 2 + q - before[k] of the last cell k with before[k] <= q;
+    // all loads are issued before any is stored, one round trip
+    float xs[kExtra], ys[kExtra];
+#pragma unroll
+    for (int q = 0; q < kExtra; ++q) {
+        int k = 0;
+        uint32_t bk = 0;
+#pragma unroll
+        for (int c = 1; c < 9; ++c) {
+            const bool later = before[c] <= (uint32_t)q;
+            k = later ? c : k;
+            bk = later ? before[c] : bk;
+        }
+        const uint32_t at = slot_at(nbhd_cell(N, k), 2u + (uint32_t)q - bk, NC);
+        xs[q] = (uint32_t)q < e ? px[at] : 0.0f;
+        ys[q] = (uint32_t)q < e ? py[at] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kExtra; ++q)
+        if ((uint32_t)q < e) ex[q] = make_float2(xs[q], ys[q]);
     N.ex = ex;
 }
 
@@ -538,20 +558,21 @@ __device__ inline int lane_features(const Nbhd &N, const float *px, const float 
     });
     const int nn = n < 12 ? n : 12;
     // ranks by (r^2, order found), all twelve squared distances read at once
-    // and compared in registers (entries from nn on are not used)
+    // and compared in registers; entries from nn on hold +inf and never count
     float r2v[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r2v[c] = scr[3 * c + 2];
+    for (int c = 0; c < 12; ++c) r2v[c] = c < nn ? scr[3 * c + 2] : INFINITY;
     if (Xrow) zero_row(Xrow);
     if (Frow)
         for (int k = 0; k < 24; ++k) Frow[k] = 0.0f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         if (c < nn) {
+            // earlier entries count on equal r^2 (order found breaks ties)
             int rank = 0;
 #pragma unroll
             for (int e = 0; e < 12; ++e)
-                rank += (e < nn && (r2v[e] < r2v[c] || (r2v[e] == r2v[c] && e < c))) ? 1 : 0;
+                if (e != c) rank += (e < c ? r2v[e] <= r2v[c] : r2v[e] < r2v[c]) ? 1 : 0;
             const float dx = scr[3 * c], dy = scr[3 * c + 1];
             if (Xrow) {
                 Xrow[2 * rank] = f2bf(dx);
