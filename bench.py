@@ -34,6 +34,9 @@ ETA = 0.716
 # four xors: 80), slot pick and step (7), new position (2), in-cell test (4),
 # accept (2): 95; plus one pair test (2 subtractions, 2 multiplications, 1
 # addition, 1 comparison: 6) per other disk of the 3 x 3 cell neighbourhood.
+# Philox's key schedule (nine additions of the Weyl constants per block) is not
+# counted: the key is the seed, the same in every lane, so the round keys are
+# scalar values that no vector lane computes.
 ALU_OPS_TRIAL = 95
 ALU_OPS_PAIR = 6
 
@@ -51,6 +54,11 @@ def alu_ops_per_trial(N, M):
     return ALU_OPS_TRIAL + ALU_OPS_PAIR * (9.0 * N / (M * M) - 1.0)
 
 
+def max_step(box):
+    """The largest step m the box allows: cell width plus step below 4."""
+    return min(255, int(math.ceil((4.0 - box.info()["w"]) * 256.0)) - 1)
+
+
 def tune_step(box, target=0.30, rounds=6, block=100):
     """Equilibration-only step tuning: m <- round(m * acc / target)."""
     m = box.info()["step_m"]
@@ -58,7 +66,7 @@ def tune_step(box, target=0.30, rounds=6, block=100):
     for _ in range(rounds):
         t, a = box.sweep(block, counts=True)
         acc = a / t
-        new = max(1, min(255, int(round(m * acc / target))))
+        new = max(1, min(max_step(box), int(round(m * acc / target))))
         if new == m:
             break
         m = new
@@ -171,7 +179,8 @@ def train_learner(side, eta, seed, step_factor=LEARN_STEP_FACTOR):
     tb = mp.Box(side * side, eta, seed=seed + 1, step_m=40, cell_min=3.0, schedule="simple")
     m_train, _ = tune_step(tb)
     tb.sweep(2000)
-    tb.set_step(min(255, step_factor * m_train))
+    m_collect = min(max_step(tb), step_factor * m_train)
+    tb.set_step(m_collect)
     L = mp.Learner(seed=seed + 2, capacity=1 << 22)
     n = 0
     while n < (1 << 21):
@@ -180,7 +189,7 @@ def train_learner(side, eta, seed, step_factor=LEARN_STEP_FACTOR):
     loss0 = L.train(1, batch=8192, lr=2e-3)
     loss = L.train(3000, batch=8192, lr=1e-3)
     torch.cuda.synchronize()
-    return L, {"moves": n, "step_m": min(255, step_factor * m_train), "tuned_step_m": m_train,
+    return L, {"moves": n, "step_m": m_collect, "tuned_step_m": m_train,
                "adam_steps": 3001, "batch": 8192, "loss_first": loss0, "loss_last": loss,
                "seconds": time.perf_counter() - t0}
 
@@ -322,6 +331,9 @@ def tau_compare_bench(args):
                                                   base["decorrelations_per_s"],
         "gain_decorrelations_per_s_vs_plain_w2_fused": lr["decorrelations_per_s"] /
                                                         out["plain_w2_fused"]["decorrelations_per_s"],
+        "command": "python3 bench.py --workload tau-compare --tc-side %d --tc-eta %.2f --tc-sweeps %d "
+                   "--tc-equil %d --tc-every %d --tc-eps %.2f" % (side, eta, sweeps, equil, every,
+                                                               args.tc_eps),
     }
     print(json.dumps(line))
 

@@ -298,3 +298,33 @@ def test_gpu_n2_closed_form_pressure(gpu_lib):
     res = g.measure_pressure()
     exact = 4 * eta / math.pi * (1 - eta) / (1 - 2 * eta)
     assert abs(res["P_star"] - exact) < 3 * res["se"], (res, exact)
+
+
+def test_validate_counts_hand_placed_overlaps(gpu_lib):
+    """mpmc_validate on hand-placed pairs: at 1.9 sigma, across the periodic
+    edge at 1.06 sigma, at 2 - q (fp32 r^2 < 4), at exactly fp32 r^2 = 4
+    (contact: no overlap) and a triple with two overlapping pairs: five
+    overlaps, as the oracle counts them."""
+    Q22 = 2 ** 22
+    g = gpu_lib.Box(16, 0.008, seed=1, lattice="none", schedule="simple")
+    Lq = g.info()["W"] * g.info()["M"]
+    pts = [(10 * Q22, 10 * Q22), (10 * Q22 + int(1.9 * Q22), 10 * Q22),
+           (Q22 // 2, 20 * Q22), (Lq - Q22 // 4, 20 * Q22 + 3 * Q22 // 4),
+           (30 * Q22, 5 * Q22), (30 * Q22 + 2 * Q22 - 1, 5 * Q22),
+           (5 * Q22, 30 * Q22), (5 * Q22, 32 * Q22),
+           (20 * Q22, 30 * Q22), (21 * Q22, 30 * Q22), (22 * Q22 + Q22 // 2, 30 * Q22)]
+    X = np.array([p[0] for p in pts] + [(40 + 5 * k) * Q22 for k in range(16 - len(pts))], np.int64)
+    Y = np.array([p[1] for p in pts] + [40 * Q22] * (16 - len(pts)), np.int64)
+    g.set_positions_q(X, Y)
+    o = OracleBox(16, 0.008, lattice=2)
+    o.set_positions_q(X, Y)
+    assert o.count_overlaps() == 5
+    assert g.validate() == (5, 0)
+    # every pair but the contact one moved apart: no overlap remains
+    for k in range(len(pts)):
+        if k not in (6, 7):
+            X[k], Y[k] = (10 + 5 * k) * Q22, 60 * Q22
+    g.set_positions_q(X, Y)
+    o.set_positions_q(X, Y)
+    assert o.count_overlaps() == 0
+    assert g.validate() == (0, 0)
