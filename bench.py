@@ -251,7 +251,9 @@ def phases_bench(args):
     print(json.dumps({"workload": "phase profile of the sweep kernel, N=1024^2 eta=0.716, "
                                   "step m=%d, tile %d, 50 sweeps" % (step_m, info["tile"]),
                       "tile": info["tile"], "us_per_tile": ph,
-                      "share": {k: v / ph["tile"] for k, v in ph.items() if k != "tile"},
+                      "share": {k: ph[k] / ph["tile"] for k in ("load", "pass1", "pass2", "pass3",
+                                                                 "pass4", "rebin_classes",
+                                                                 "rebin_scatter")},
                       "kernel_digest": kernel_source_digest()}))
 
 
@@ -961,6 +963,9 @@ def main():
     ap.add_argument("--tc-equil", type=int, default=20000)
     ap.add_argument("--tc-every", type=int, default=40)
     ap.add_argument("--tc-eps", type=float, default=0.1)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="fix the fused sweep's tile (cells per side) instead of autotuning it; "
+                         "for counter runs, whose serialised launches distort the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -1003,6 +1008,7 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular",
+                     schedule="fused" if args.tile else "auto", tile=args.tile,
                      stream=stream.cuda_stream)
         box.set_graphs(args.sweeps)  # one captured graph per benchmark step
         step_m, acc0 = tune_step(box)

@@ -336,15 +336,24 @@ int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t thr
 
 /* Phase profile of the fused sweep kernel: runs `sweeps` sweeps (the chain
  * advances exactly as with mpmc_sweep), each workgroup recording the device
- * realtime clock at its phase boundaries, and returns in phase_us[8] the
- * mean duration per tile in microseconds of: the region load, colour passes
- * 1-4 (in sweep order), the re-bin's class counts, its scatter, and the
- * whole tile.  Allocates a stamp buffer for the call.  MPMC_EINVAL unless
+ * realtime clock at its entry and at its phase boundaries, and returns in
+ * phase_us[12]: [0..7] the mean duration per tile in microseconds of the
+ * region load, colour passes 1-4 (in sweep order), the re-bin's class
+ * counts, its scatter and the whole tile; [8] the mean time per tile from
+ * the workgroup's entry to the start of its work (reading the sweep counter
+ * and drawing the sweep's shift and colour order); per launch, averaged over
+ * the sweeps: [9] the span from the first workgroup's entry to the last
+ * one's end (us), [10] the mean number of tiles in flight over that span
+ * (summed entry-to-end time / span), [11] the time from the first entry to
+ * the last (us).  Allocates a stamp buffer for the call.  MPMC_EINVAL unless
  * the box runs the fused schedule. */
 int mpmc_profile_phases(mpmc_box b, uint32_t sweeps, double *phase_us);
 
 /* Long runs replay a captured HIP graph of this many sweeps (even, default
- * 128 fused / 32 simple); 0 launches every sweep directly. */
+ * 128 fused / 32 simple); 0 launches every sweep directly.  Learned sweeps
+ * (mpmc_sweep_learned) replay graphs of 8 sweeps while graphs are on (any
+ * nonzero value) and launch every sweep directly when they are off; either
+ * way the trajectory is the same. */
 int mpmc_set_graphs(mpmc_box b, uint32_t sweeps_per_graph);
 
 /* ---- batches of independent boxes ----------------------------------------

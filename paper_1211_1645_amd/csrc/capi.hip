@@ -120,6 +120,8 @@ void Box::release() {
     meas_pending = false;
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;
+    if (lgraph_exec) (void)hipGraphExecDestroy(lgraph_exec);
+    lgraph_exec = nullptr;
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     for (void *a : allocations) {
@@ -556,7 +558,7 @@ extern "C" int mpmc_profile_phases(mpmc_box bh, uint32_t sweeps, double *phase_u
     if (b->sched != MPMC_SCHED_FUSED)
         return fail(MPMC_EINVAL, "phase profiles need the fused schedule");
     const uint32_t nt = (b->g.M + b->shape.tile - 1) / b->shape.tile;
-    const size_t words = (size_t)nt * nt * 8;
+    const size_t tiles = (size_t)nt * nt, words = tiles * kStampWords;
     unsigned long long *d = nullptr;
     int rc = b->alloc_dev((void **)&d, words * 8);
     if (rc) return rc;
@@ -564,7 +566,10 @@ extern "C" int mpmc_profile_phases(mpmc_box bh, uint32_t sweeps, double *phase_u
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     std::vector<unsigned long long> h(words);
-    double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // per tile: the seven phases, the whole tile, entry to start of work;
+    // per launch: first entry to last end, busy tile-time over that span,
+    // first entry to last entry
+    double sum[12] = {};
     rc = b->join_meas();
     for (uint32_t k = 0; k < sweeps && rc == MPMC_OK && e == hipSuccess; ++k) {
         // one sweep as mpmc_sweep launches it outside a graph, with stamps
@@ -583,17 +588,31 @@ extern "C" int mpmc_profile_phases(mpmc_box bh, uint32_t sweeps, double *phase_u
         b->cur ^= 1;
         ++b->host_sweeps;
         b->canon_in_c = true;
-        for (size_t t = 0; t < (size_t)nt * nt; ++t) {
-            const unsigned long long *w = &h[8 * t];
+        unsigned long long first = ~0ull, last_entry = 0, last_end = 0;
+        double busy = 0;
+        for (size_t t = 0; t < tiles; ++t) {
+            const unsigned long long *w = &h[kStampWords * t];
             for (int ph = 0; ph < 7; ++ph) sum[ph] += (double)(long long)(w[ph + 1] - w[ph]);
             sum[7] += (double)(long long)(w[7] - w[0]);
+            sum[8] += (double)(long long)(w[0] - w[8]);
+            busy += (double)(long long)(w[7] - w[8]);
+            first = w[8] < first ? w[8] : first;
+            last_entry = w[8] > last_entry ? w[8] : last_entry;
+            last_end = w[7] > last_end ? w[7] : last_end;
         }
+        const double span = (double)(long long)(last_end - first);
+        sum[9] += span;
+        sum[10] += span > 0 ? busy / span : 0.0;
+        sum[11] += (double)(long long)(last_entry - first);
     }
     b->free_dev(d);
     if (rc) return rc;
     if (e != hipSuccess) return fail(MPMC_EDEVICE, "phase profile: %s", hipGetErrorString(e));
     const double us_per_tick = 1e3 / (double)(khz > 0 ? khz : 100000);
-    for (int ph = 0; ph < 8; ++ph) phase_us[ph] = sum[ph] / ((double)nt * nt * sweeps) * us_per_tick;
+    for (int ph = 0; ph < 9; ++ph) phase_us[ph] = sum[ph] / ((double)tiles * sweeps) * us_per_tick;
+    phase_us[9] = sum[9] / sweeps * us_per_tick;
+    phase_us[10] = sum[10] / sweeps;
+    phase_us[11] = sum[11] / sweeps * us_per_tick;
     return MPMC_OK;
 }
 

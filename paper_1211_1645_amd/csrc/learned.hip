@@ -1459,6 +1459,53 @@ extern "C" int mpmc_learned_features(mpmc_box bh, const uint32_t *tags, uint32_t
 // update per sweep.  With `stamps` (room for the waves of one pass) each
 // sweep is synchronised and the phase durations of every wave of every pass
 // are added to phase_ticks[kLearnStamps - 1].
+// A run of learned sweeps replays a captured graph of this many sweeps (even:
+// the double-buffered lists return to the buffer they started in) while the
+// box uses graphs; shorter remainders are launched one sweep at a time.
+constexpr uint32_t kLearnGraphSweeps = 8;
+
+// Learned sweep j of a run that starts at the device's sweep counter with the
+// lists in P[from]: the four colour passes update those lists in place, then
+// the re-bin writes them into the other buffer in the grid of sweep j + 1.
+// The counter is advanced by the caller.
+static void launch_learned_sweep(Box *b, int from, uint32_t j, const LearnView &lv, uint32_t grid,
+                                 size_t lds, hipStream_t st) {
+    BoxView v = b->view(from);
+    v.offset = j;
+    const BoxView pv = in_place(v);
+    for (uint32_t p = 0; p < 4; ++p) k_pass_learned<<<grid, 64 * kLearnWaves, lds, st>>>(pv, p, lv);
+    v.offset = j + 1;
+    launch_rebin(v, st);
+}
+
+// The box's graph of kLearnGraphSweeps learned sweeps from P[0] and the
+// counter update after them, captured again when the learner or the branch
+// threshold differs from the last capture.
+static int learned_graph(Box *b, const LearnView &lv, uint32_t grid, size_t lds) {
+    if (b->lgraph_exec && b->lgraph_W == (const void *)lv.W && b->lgraph_over == (const void *)lv.nfeat_over &&
+        b->lgraph_E == lv.E)
+        return MPMC_OK;
+    if (b->lgraph_exec) (void)hipGraphExecDestroy(b->lgraph_exec);
+    b->lgraph_exec = nullptr;
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (uint32_t j = 0; j < kLearnGraphSweeps; ++j)
+        launch_learned_sweep(b, (int)(j & 1u), j, lv, grid, lds, b->cap_stream);
+    launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
+                   kLearnGraphSweeps, b->cap_stream);
+    HIPCHK(hipStreamEndCapture(b->cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&b->lgraph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        b->lgraph_exec = nullptr;
+        return fail(MPMC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->lgraph_W = lv.W;
+    b->lgraph_over = lv.nfeat_over;
+    b->lgraph_E = lv.E;
+    return MPMC_OK;
+}
+
 static int learned_sweeps(Box *b, Learner *l, uint64_t k, float eps, unsigned long long *stamps,
                           double *phase_ticks) {
     const size_t lds = sizeof(LdsLearn);
@@ -1472,14 +1519,25 @@ static int learned_sweeps(Box *b, Learner *l, uint64_t k, float eps, unsigned lo
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
     constexpr uint32_t nt = 64 * kLearnWaves;
     const uint32_t grid = (na + nt - 1) / nt, waves = grid * kLearnWaves;
+    const LearnView lv{l->W, E, ldexp((double)E, -32), l->over, stamps};
     std::vector<unsigned long long> h(stamps ? (size_t)waves * kLearnStamps : 0);
-    for (uint64_t s = 0; s < k; ++s) {
-        BoxView v = b->view(b->cur);
-        const BoxView pv = in_place(v);
-        for (uint32_t p = 0; p < 4; ++p) {
-            LearnView lv{l->W, E, ldexp((double)E, -32), l->over, stamps};
-            k_pass_learned<<<grid, nt, lds, b->stream>>>(pv, p, lv);
-            if (stamps) {
+    for (uint64_t s = 0; s < k;) {
+        if (!stamps && b->use_graphs && b->cur == 0 && k - s >= kLearnGraphSweeps) {
+            int rc = learned_graph(b, lv, grid, lds);
+            if (rc) return rc;
+            HIPCHK(hipGraphLaunch(b->lgraph_exec, b->stream));
+            s += kLearnGraphSweeps;
+            b->canon_in_c = false;
+            continue;
+        }
+        if (!stamps) {
+            launch_learned_sweep(b, b->cur, 0, lv, grid, lds, b->stream);
+        } else {
+            // one pass at a time, each followed by the read-back of its stamps
+            BoxView v = b->view(b->cur);
+            const BoxView pv = in_place(v);
+            for (uint32_t p = 0; p < 4; ++p) {
+                k_pass_learned<<<grid, nt, lds, b->stream>>>(pv, p, lv);
                 HIPCHK(hipMemcpyAsync(h.data(), stamps, h.size() * 8, hipMemcpyDeviceToHost, b->stream));
                 HIPCHK(hipStreamSynchronize(b->stream));
                 for (uint32_t w = 0; w < waves; ++w)
@@ -1487,14 +1545,15 @@ static int learned_sweeps(Box *b, Learner *l, uint64_t k, float eps, unsigned lo
                         phase_ticks[ph] += (double)(long long)(h[(size_t)w * kLearnStamps + ph + 1] -
                                                                h[(size_t)w * kLearnStamps + ph]);
             }
+            v.offset = 1;  // binned for the next sweep
+            launch_rebin(v, b->stream);
         }
-        v.offset = 1;  // binned for the next sweep
-        launch_rebin(v, b->stream);
         launch_advance(b->dev, (uint32_t)b->seed, (uint32_t)(b->seed >> 32), (uint32_t)b->g.W, b->g.Lq,
                        1, b->stream);
         HIPCHK(hipGetLastError());
         b->cur ^= 1;
         b->canon_in_c = false;
+        ++s;
     }
     return MPMC_OK;
 }
@@ -1507,9 +1566,12 @@ extern "C" int mpmc_sweep_learned(mpmc_box bh, mpmc_learner lh, uint64_t k, floa
     Learner *l = LR(lh);
     int rc = check_learned_box(b);
     if (rc) return rc;
-    rc = b->read_scalars();
-    if (rc) return rc;
-    const DevScalars before = b->host;
+    DevScalars before{};
+    if (trials || accepts) {
+        rc = b->read_scalars();
+        if (rc) return rc;
+        before = b->host;
+    }
     rc = learned_sweeps(b, l, k, eps, nullptr, nullptr);
     if (rc) return rc;
     if (trials || accepts) {

@@ -79,6 +79,11 @@ struct Box {
     bool use_graphs = true;
     uint32_t graph_sweeps = 64;
     hipGraphExec_t graph_exec = nullptr;  // all sweeps of a run but the last
+    // learned sweeps: a captured run of them, and the learner weights, feature
+    // overflow counter and uniform-branch threshold it was captured with
+    hipGraphExec_t lgraph_exec = nullptr;
+    const void *lgraph_W = nullptr, *lgraph_over = nullptr;
+    uint64_t lgraph_E = 0;
     // Asynchronous measurement: its kernels run on meas_stream and read only
     // the canonical buffers C; every later write of C, and every other use of
     // the measurement buffers, first waits for ev_meas on the box's stream.

@@ -44,8 +44,9 @@ void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_
 struct FusedShape { uint32_t tile, threads; };
 bool fused_supported(const BoxView &v, const FusedShape &s);
 const FusedShape *fused_shapes(uint32_t *count);
-// stamps (NULL normally): eight realtime-clock words per tile, for the
-// phase profile
+// stamps (NULL normally): kStampWords realtime-clock words per tile, for
+// the phase profile
+constexpr uint32_t kStampWords = 9;
 void launch_fused_sweep(const BoxView &v, const FusedShape &s, hipStream_t st,
                         unsigned long long *stamps = nullptr);
 // views[2 b + parity]: box b read from buffer `parity`; items: box << 20 | tile

@@ -271,9 +271,11 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
     }
 }
 
-// Phase profiling: with a non-NULL `stamp` (eight words per tile), thread 0
-// records the realtime clock when the tile starts, after the region load,
-// after each colour pass, after the re-bin's class counts and at the end.
+// Phase profiling: with a non-NULL `stamp` (kStampWords words per tile),
+// thread 0 records the realtime clock when the tile's work starts, after the
+// region load, after each colour pass, after the re-bin's class counts and at
+// the end (words 0-7); word 8 is written by the kernel when its workgroup
+// enters, before it reads the sweep counter.
 __device__ __forceinline__ void stamp_at(unsigned long long *stamp, int tid, int k) {
     if (stamp && tid == 0) stamp[k] = wall_clock64();
 }
@@ -521,8 +523,9 @@ __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint
     // contiguous run of tiles so that shared halo cells meet in its L2.
     const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
     if (tile >= ntx * nty) return;
-    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE,
-                              stamps ? stamps + 8 * (size_t)tile : nullptr);
+    unsigned long long *stamp = stamps ? stamps + kStampWords * (size_t)tile : nullptr;
+    stamp_at(stamp, (int)threadIdx.x, 8);
+    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE, stamp);
 }
 
 // Persistent form for a batch of independent boxes: workgroups stride over

@@ -273,12 +273,14 @@ class Box:
         _check(_lib.mpmc_set_graphs(self.h, sweeps_per_graph))
 
     PHASES = ("load", "pass1", "pass2", "pass3", "pass4", "rebin_classes", "rebin_scatter",
-              "tile")
+              "tile", "entry_to_work", "launch_span", "tiles_in_flight", "last_entry")
 
     def profile_phases(self, sweeps=20):
         """Mean microseconds per tile of each phase of the fused sweep
-        kernel (the box advances by `sweeps` sweeps)."""
-        out = np.zeros(8, np.float64)
+        kernel, and per launch its span, mean tiles in flight and the time
+        to its last workgroup's entry (the box advances by `sweeps`
+        sweeps)."""
+        out = np.zeros(12, np.float64)
         _check(_lib.mpmc_profile_phases(self.h, sweeps, _ptr(out)))
         return dict(zip(self.PHASES, out.tolist()))
 

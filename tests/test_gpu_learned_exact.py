@@ -191,3 +191,26 @@ def test_adam_matches_oracle(gpu_lib):
     got = L.params().astype(np.float64)
     assert np.abs(got - p).max() < 2e-6, np.abs(got - p).max()
     assert np.abs(got - p0).max() > 5e-3  # the steps did move the weights
+
+
+def test_learned_graph_replays_match_direct_launches(gpu_lib):
+    """Runs of learned sweeps replay captured graphs of 8 sweeps; with graphs
+    off every sweep is launched directly.  Both give the same trajectory and
+    counts, from an odd start (direct sweeps until the lists are back in
+    their first buffer), across a change of eps (a new capture) and a new
+    learner."""
+    L = gpu_lib.Learner(seed=1, capacity=16)
+    L.set_params(inputs.mlp_params(8))
+    a = gpu_lib.Box(4096, 0.70, seed=5, step_m=40, cell_min=3.0, schedule="simple")
+    b = gpu_lib.Box(4096, 0.70, seed=5, step_m=40, cell_min=3.0, schedule="simple")
+    b.set_graphs(0)
+    for k, eps in ((1, 0.1), (19, 0.1), (16, 0.3), (8, 0.3)):
+        assert (gpu_lib.sweep_learned(a, L, k, eps=eps, counts=True) ==
+                gpu_lib.sweep_learned(b, L, k, eps=eps, counts=True))
+    L2 = gpu_lib.Learner(seed=2, capacity=16)
+    L2.set_params(inputs.mlp_params(9))
+    assert (gpu_lib.sweep_learned(a, L2, 24, eps=0.2, counts=True) ==
+            gpu_lib.sweep_learned(b, L2, 24, eps=0.2, counts=True))
+    for x, y in zip(a.cells(), b.cells()):
+        assert np.array_equal(x, y)
+    assert a.validate() == (0, 0)
