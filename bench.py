@@ -195,37 +195,38 @@ def train_learner(side, eta, seed, step_factor=LEARN_STEP_FACTOR):
 
 
 def psi6_runs(make_box, advance, runs, equil, sweeps, every, label):
-    """`runs` independent boxes, each on a stream of its own so that the
-    small boxes run side by side: `equil` sweeps, then `sweeps` more with
-    Psi_6 every `every`.  Returns (series per run, elapsed seconds of the
-    measured part, trials per disk and sweep)."""
+    """`runs` independent boxes, one after the other, each with the GPU to
+    itself: `equil` sweeps, then `sweeps` more with Psi_6 every `every`.
+    Returns (series per run, elapsed seconds of the measured parts, trials
+    per disk and sweep).  The runs are not overlapped on several streams:
+    on this GPU kernels of at most two streams ran concurrently, so three
+    boxes side by side took twice as long as one, whatever the sampler."""
     import numpy as np
     import torch
-    streams = [torch.cuda.Stream() for _ in range(runs)]
-    boxes = []
-    for r in range(runs):
-        with torch.cuda.stream(streams[r]):
-            boxes.append(make_box(r, streams[r].cuda_stream))
-    for b in boxes:
-        advance(b, equil)
-    torch.cuda.synchronize()
-    i0 = [b.info() for b in boxes]
     n = sweeps // every
     series = np.zeros((runs, n), np.complex128)
-    t0 = time.perf_counter()
-    last = t0
-    for k in range(n):
-        for b in boxes:
+    elapsed, trials = 0.0, 0
+    stream = torch.cuda.Stream()
+    for r in range(runs):
+        with torch.cuda.stream(stream):
+            b = make_box(r, stream.cuda_stream)
+        advance(b, equil)
+        torch.cuda.synchronize()
+        i0 = b.info()
+        t0 = time.perf_counter()
+        last = t0
+        for k in range(n):
             advance(b, every)
-        for r, b in enumerate(boxes):
             series[r, k] = b.psi6()
-        if time.perf_counter() - last > 30:
-            last = time.perf_counter()
-            progress("%s: %d of %d sweeps" % (label, (k + 1) * every, sweeps))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    i1 = [b.info() for b in boxes]
-    disp = sum(a["trials"] - z["trials"] for a, z in zip(i1, i0)) / (runs * n * every * boxes[0].N)
+            if time.perf_counter() - last > 30:
+                last = time.perf_counter()
+                progress("%s run %d: %d of %d sweeps" % (label, r, (k + 1) * every, sweeps))
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        trials += b.info()["trials"] - i0["trials"]
+        N = b.N
+        del b
+    disp = trials / (runs * n * every * N)
     return series, elapsed, disp
 
 
@@ -264,8 +265,8 @@ def tau_compare_bench(args):
     long after equilibration.  Samplers: plain on the w >= 3 grid (the
     learned proposal's grid), plain on its own w >= 2 grid (the fused
     kernel), learned on the w >= 3 grid.  tau is the e-folding lag of
-    C(dt); the rate is sweeps per second of the runs side by side divided by
-    tau in sweeps."""
+    C(dt); the rate is sweeps per second, each run alone on the GPU, divided
+    by tau in sweeps."""
     import numpy as np
     import paper_1211_1645_amd.mpmc as mp
     side, eta, R = args.tc_side, args.tc_eta, 3
@@ -305,7 +306,8 @@ def tau_compare_bench(args):
         tm, tse = float(np.mean(taus)), float(np.std(taus, ddof=1) / math.sqrt(R))
         out[name] = {"tau_sweeps_runs": taus.tolist(), "tau_sweeps": tm, "tau_sweeps_se": tse,
                      "tau_trials_per_disk": tm * disp, "tau_trials_per_disk_se": tse * disp,
-                     "trials_per_disk_per_sweep": disp, "sweeps_per_s_all_runs": rate,
+                     "trials_per_disk_per_sweep": disp, "sweeps_per_s": rate,
+                     "us_per_sweep": 1e6 / rate,
                      "decorrelations_per_s": rate / tm,
                      "decorrelations_per_s_se": rate / tm * tse / tm,
                      "abs_Psi6_mean": float(np.abs(series).mean()),
@@ -321,8 +323,9 @@ def tau_compare_bench(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (sampler), f64 (proposal law)",
         "data": "synthetic (triangular-lattice starts, Philox4x32-10 seeds %d..)" % args.seed,
-        "config": {"workload": "Psi6 decorrelation, N=%d^2 eta=%.2f, %d runs per sampler side "
-                               "by side, %d sweeps each after %d, Psi6 every %d; learned eps=%.2f"
+        "config": {"workload": "Psi6 decorrelation, N=%d^2 eta=%.2f, %d runs per sampler one "
+                               "after the other, %d sweeps each after %d, Psi6 every %d; learned "
+                               "eps=%.2f"
                                % (side, eta, R, sweeps, equil, every, args.tc_eps),
                    "N": side * side, "eta": eta, "step_m_w3": m3, "step_m_w2": m2},
         "train": train,
