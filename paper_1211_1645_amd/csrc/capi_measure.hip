@@ -228,6 +228,14 @@ extern "C" int mpmc_contact_hist_subset(mpmc_box bh, const uint8_t *sel, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// psi_j by tag (re[N], im[N]), the cell field (re, im[M * M]) and psi_j by
+// cell slot (re, im[CS * M * M]), allocated on first use.
+int Box::psi_work() {
+    if (psi_buf) return MPMC_OK;
+    const size_t nc = (size_t)g.M * g.M;
+    return alloc_dev((void **)&psi_buf, (2 * (size_t)N + 2 * nc + 2 * nc * g.CS) * 4);
+}
+
 extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, float *fim,
                                double *Psi_re, double *Psi_im, int on_device) {
     if (!bh) return fail(MPMC_EINVAL, "NULL box");
@@ -236,11 +244,9 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
     if (b->N < 7) return fail(MPMC_EINVAL, "psi_6 needs at least 7 disks");
     const uint32_t M = b->g.M;
     const size_t nc = (size_t)M * M;
-    if (!b->psi_buf) {
-        int rc = b->alloc_dev((void **)&b->psi_buf, (2 * (size_t)b->N + 2 * nc) * 4);
-        if (rc) return rc;
-    }
+    if (int rc = b->psi_work()) return rc;
     float *dre = b->psi_buf, *dim = dre + b->N, *dfr = dim + b->N, *dfi = dfr + nc;
+    float *dsr = dfi + nc, *dsi = dsr + nc * b->g.CS;
     const uint32_t hmax = (M - 2) / 2;  // 2h + 1 <= M - 1: no cell seen twice
     uint32_t h = hmax < 2 ? hmax : 2;
     if (h < 1) return fail(MPMC_EINVAL, "box too small for the neighbour search");
@@ -257,9 +263,10 @@ extern "C" int mpmc_psi6_field(mpmc_box bh, float *re, float *im, float *fre, fl
         }
         HIPCHK(hipMemsetAsync(&b->dev->psi_re, 0, 16, b->stream));
         HIPCHK(hipMemsetAsync(b->scratch_u32, 0, 4, b->stream));
-        launch_psi6(b->mview(), h, dre, dim, b->scratch_u32, b->loc, b->meas_work, b->stream);
+        launch_psi6(b->mview(), h, dre, dim, dsr, dsi, b->scratch_u32, b->loc, b->meas_work, b->stream);
         HIPCHK(hipGetLastError());
-        launch_psi6_field(b->mview(), dre, dim, dfr, dfi, b->stream);
+        if (measure_tiled(b->mview(), h)) launch_psi6_field_slots(b->mview(), dsr, dsi, dfr, dfi, b->stream);
+        else launch_psi6_field(b->mview(), dre, dim, dfr, dfi, b->stream);
         HIPCHK(hipGetLastError());
         const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (re) HIPCHK(hipMemcpyAsync(re, dre, (size_t)b->N * 4, kind, b->stream));
@@ -296,7 +303,8 @@ int Box::measure_async(double *Psi_dev, bool field) {
     // as mpmc_psi6_field: stencil 2 first, then the widest staged stencil,
     // but the second pass is launched always and decides on the device
     // whether it has anything to do (a wider stencil finds the same six
-    // nearest, so the result does not depend on which pass produced it)
+    // nearest, summed in its own stencil order; both paths keep the first
+    // stencil that suffices, so they agree bit for bit)
     const uint32_t hmax = (g.M - 2) / 2;
     const uint32_t hp = hmax < (uint32_t)kAsyncPsiHalo ? hmax : (uint32_t)kAsyncPsiHalo;
     const uint32_t h1 = hp < 2u ? hp : 2u;
@@ -307,10 +315,8 @@ int Box::measure_async(double *Psi_dev, bool field) {
     rc = measure_work();
     if (rc) return rc;
     const size_t nc = (size_t)g.M * g.M;
-    if (!psi_buf) {
-        rc = alloc_dev((void **)&psi_buf, (2 * (size_t)N + 2 * nc) * 4);
-        if (rc) return rc;
-    }
+    rc = psi_work();
+    if (rc) return rc;
     if (!async_fail) {  // [0]: verdict reported by mpmc_measure_wait, [1]: first pass
         rc = alloc_dev((void **)&async_fail, 8);
         if (rc) return rc;
@@ -328,15 +334,17 @@ int Box::measure_async(double *Psi_dev, bool field) {
     HIPCHK(hipGetLastError());
     ++n_conf;
     float *dre = psi_buf, *dim = dre + N, *dfr = dim + N, *dfi = dfr + nc;
+    float *dsr = dfi + nc, *dsi = dsr + nc * g.CS;
     if (h1 < hp) {
         HIPCHK(hipMemsetAsync(async_fail + 1, 0, 4, meas_stream));
-        launch_psi6_retry(m, h1, hp, dre, dim, async_fail + 1, async_fail, meas_work, meas_stream);
+        launch_psi6_retry(m, h1, hp, dre, dim, dsr, dsi, async_fail + 1, async_fail, meas_work,
+                          meas_stream);
     } else {
-        launch_psi6(m, hp, dre, dim, async_fail, loc, meas_work, meas_stream);
+        launch_psi6(m, hp, dre, dim, dsr, dsi, async_fail, loc, meas_work, meas_stream);
     }
     HIPCHK(hipGetLastError());
-    if (field) {
-        launch_psi6_field(m, dre, dim, dfr, dfi, meas_stream);
+    if (field) {  // the staged kernels ran (checked above): psi_j by cell slot is there
+        launch_psi6_field_slots(m, dsr, dsi, dfr, dfi, meas_stream);
         HIPCHK(hipGetLastError());
     }
     if (Psi_dev) {

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_contact_hist(MeasureView m, const float
 // no two workgroups add to one address.
 constexpr int kPT = 16, kStageHalo = 3, kSR = kPT + 2 * kStageHalo;
 constexpr float kFarM = 1.0e6f;  // sentinel offset of an empty slot
-constexpr uint32_t kMeasGrid = 1024;
+constexpr uint32_t kMeasGrid = 1536;  // six workgroups per CU, as LDS allows
 
 struct Stage {
     float4 x[kSR * kSR], y[kSR * kSR];
@@ -171,7 +171,7 @@ __device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t
 
 // Ordered contact pairs of the listed disks into the LDS bins.
 template <int H, int SL>
-__device__ void contact_disks(const Stage &S, const MeasureView &m, const float *__restrict__ E,
+__device__ void contact_disks(const Stage &S, const MeasureView &m, const float *E,
                               uint32_t K, const uint8_t *sel, int ndisk, uint32_t *bins) {
     constexpr int SR = kPT + 2 * H;
     const float e0 = E[0], eK = E[K];
@@ -207,19 +207,23 @@ __device__ void contact_disks(const Stage &S, const MeasureView &m, const float 
     }
 }
 
+// Dynamic LDS: K bins, then the K + 1 squared edges, so that settling a
+// pair on its bin reads no global memory.
 template <int H>
 __global__ void __launch_bounds__(256) k_contact_hist_tile(MeasureView m, const float *__restrict__ E,
                                                            uint32_t K, const uint8_t *sel,
                                                            uint32_t *rows) {
     __shared__ Stage S;
     extern __shared__ uint32_t bins[];
+    float *El = reinterpret_cast<float *>(bins + K);
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
+    for (uint32_t k = threadIdx.x; k <= K; k += blockDim.x) El[k] = E[k];
     const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
     for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
         bool big;
         const int nd = stage_block<H>(S, m, (blk % nbx) * kPT, (blk / nbx) * kPT, &big);
-        if (big) contact_disks<H, 4>(S, m, E, K, sel, nd, bins);
-        else contact_disks<H, 2>(S, m, E, K, sel, nd, bins);
+        if (big) contact_disks<H, 4>(S, m, El, K, sel, nd, bins);
+        else contact_disks<H, 2>(S, m, El, K, sel, nd, bins);
         __syncthreads();  // S is restaged for the next block
     }
     for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) rows[blockIdx.x * K + k] = bins[k];
@@ -244,7 +248,7 @@ void launch_contact_tiled(const MeasureView &m, const float *edges, uint32_t K, 
     const uint32_t nb = (m.M + kPT - 1) / kPT;
     const uint32_t G = nb * nb < kMeasGrid ? nb * nb : kMeasGrid;
     uint32_t *rows = static_cast<uint32_t *>(work);
-    const size_t lds = K * sizeof(uint32_t);
+    const size_t lds = (2 * (size_t)K + 1) * sizeof(uint32_t);
     if (h == 1) k_contact_hist_tile<1><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
     else if (h == 2) k_contact_hist_tile<2><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
     else k_contact_hist_tile<3><<<G, 256, lds, st>>>(m, edges, K, sel, rows);
@@ -368,9 +372,18 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
 }
 
 // psi_j of the listed disks; returns this lane's contribution to the sums.
+// The six nearest by (fp32 r^2, tag) are kept sorted as 64-bit keys
+// r^2 bits << 32 | tag (r^2 >= 0, so its bits order as the value), each with
+// its place in the stage; a candidate is one compare against the sixth key,
+// an insertion a chain of compare-exchanges of key and place.  The
+// neighbours' offsets are recomputed from their places at the end, in the
+// same arithmetic.  Empty slots hold a far sentinel: they enter only a list
+// that then fails the reach test.  sre, sim (may be NULL) receive psi_j by
+// cell slot as well.
 template <int H, int SL>
-__device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, float *re, float *im,
-                           uint32_t *fail, double &pr, double &pi) {
+__device__ void psi6_disks(const Stage &S, const MeasureView &m, uint32_t I0, uint32_t J0, int ndisk,
+                           float *re, float *im, float *sre, float *sim, uint32_t *fail, double &pr,
+                           double &pi) {
     constexpr int SR = kPT + 2 * H;
     for (int j = threadIdx.x; j < ndisk; j += blockDim.x) {
         const uint32_t d = S.disk[j];
@@ -378,9 +391,13 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, floa
         const int me = (cl % kPT + H) + SR * (cl / kPT + H);
         const float xi = comp4f(S.x[me], s), yi = comp4f(S.y[me], s);
         const uint32_t ti = comp4u(S.tag[me], s);
-        Nb6 b;
+        unsigned long long key[6];
+        uint32_t at[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) { b.r2[e] = INFINITY; b.tag[e] = 0xFFFFFFFFu; b.dx[e] = 0; b.dy[e] = 0; }
+        for (int e = 0; e < 6; ++e) {
+            key[e] = ~0ull;
+            at[e] = (uint32_t)me << 2;
+        }
 #pragma unroll 1
         for (int dj = -H; dj <= H; ++dj)
 #pragma unroll
@@ -393,24 +410,35 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, floa
                 for (int q = 0; q < SL; ++q) {
                     const float dx = (comp4f(qx, q) - xi) + cwx;
                     const float dy = (comp4f(qy, q) - yi) + cwy;
-                    // empty slots hold a far sentinel: they can only enter a
-                    // list that then fails the reach test below
-                    const float r2 = r2_f32(dx, dy);
-                    const uint32_t tg = comp4u(qt, q);
+                    const unsigned long long k =
+                        ((unsigned long long)__float_as_uint(r2_f32(dx, dy)) << 32) | comp4u(qt, q);
                     const bool self = di == 0 && dj == 0 && q == s;
-                    if (self || !nb_less(r2, tg, b.r2[5], b.tag[5])) continue;
-                    b.r2[5] = r2; b.tag[5] = tg; b.dx[5] = dx; b.dy[5] = dy;
+                    if (self || !(k < key[5])) continue;
+                    key[5] = k;
+                    at[5] = ((uint32_t)ne << 2) | (uint32_t)q;
 #pragma unroll
                     for (int e = 5; e > 0; --e) {
-                        if (nb_less(b.r2[e], b.tag[e], b.r2[e - 1], b.tag[e - 1])) {
-                            float fr = b.r2[e]; b.r2[e] = b.r2[e - 1]; b.r2[e - 1] = fr;
-                            uint32_t ft = b.tag[e]; b.tag[e] = b.tag[e - 1]; b.tag[e - 1] = ft;
-                            float fx = b.dx[e]; b.dx[e] = b.dx[e - 1]; b.dx[e - 1] = fx;
-                            float fy = b.dy[e]; b.dy[e] = b.dy[e - 1]; b.dy[e - 1] = fy;
-                        }
+                        const bool sw = key[e] < key[e - 1];
+                        const unsigned long long ka = key[e], kb = key[e - 1];
+                        const uint32_t pa = at[e], pb = at[e - 1];
+                        key[e] = sw ? kb : ka;
+                        key[e - 1] = sw ? ka : kb;
+                        at[e] = sw ? pb : pa;
+                        at[e - 1] = sw ? pa : pb;
                     }
                 }
             }
+        Nb6 b;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int ne = (int)(at[e] >> 2), q = (int)(at[e] & 3u);
+            const int di = ne % SR - me % SR, dj = ne / SR - me / SR;
+            const float cwx = (float)di * m.w, cwy = (float)dj * m.w;
+            b.dx[e] = (comp4f(S.x[ne], q) - xi) + cwx;
+            b.dy[e] = (comp4f(S.y[ne], q) - yi) + cwy;
+            b.r2[e] = __uint_as_float((uint32_t)(key[e] >> 32));
+            b.tag[e] = (uint32_t)key[e];
+        }
         // exact only if every disk closer than the sixth lies in the stencil
         const double reach = (double)H * (double)m.w;
         if (!((double)b.r2[5] < reach * reach * (1.0 - 1e-6))) atomicOr(fail, 1u);
@@ -418,6 +446,12 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, floa
         psi6_sum(b, sr6, si6);
         re[ti] = sr6;
         im[ti] = si6;
+        if (sre) {
+            const uint32_t c = (I0 + (uint32_t)(cl % kPT)) + m.M * (J0 + (uint32_t)(cl / kPT));
+            const uint32_t a = (uint32_t)s * m.M * m.M + c;
+            sre[a] = sr6;
+            sim[a] = si6;
+        }
         pr += sr6;
         pi += si6;
     }
@@ -427,8 +461,8 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, int ndisk, floa
 // with the flag clear the launch does nothing and leaves that pass's psi_j
 // and partials in place.
 template <int H>
-__global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, float *im,
-                                                   uint32_t *fail, double2 *part,
+__global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, float *im, float *sre,
+                                                   float *sim, uint32_t *fail, double2 *part,
                                                    const uint32_t *gate) {
     if (gate != nullptr && *gate == 0u) return;  // uniform over the grid
     __shared__ Stage S;
@@ -437,9 +471,10 @@ __global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, flo
     double pr = 0.0, pi = 0.0;
     for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
         bool big;
-        const int nd = stage_block<H>(S, m, (blk % nbx) * kPT, (blk / nbx) * kPT, &big);
-        if (big) psi6_disks<H, 4>(S, m, nd, re, im, fail, pr, pi);
-        else psi6_disks<H, 2>(S, m, nd, re, im, fail, pr, pi);
+        const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
+        const int nd = stage_block<H>(S, m, I0, J0, &big);
+        if (big) psi6_disks<H, 4>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi);
+        else psi6_disks<H, 2>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi);
         __syncthreads();  // S is restaged for the next block
     }
 #pragma unroll
@@ -476,11 +511,11 @@ __global__ void __launch_bounds__(256) k_psi_reduce(const double2 *part, uint32_
 }
 
 namespace {
-void launch_psi6_tile(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                      double2 *part, const uint32_t *gate, uint32_t G, hipStream_t st) {
-    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
-    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
-    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, fail, part, gate);
+void launch_psi6_tile(const MeasureView &m, uint32_t h, float *re, float *im, float *sre, float *sim,
+                      uint32_t *fail, double2 *part, const uint32_t *gate, uint32_t G, hipStream_t st) {
+    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
+    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
+    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
 }
 uint32_t psi6_grid(const MeasureView &m) {
     const uint32_t nb = (m.M + kPT - 1) / kPT;
@@ -488,11 +523,11 @@ uint32_t psi6_grid(const MeasureView &m) {
 }
 }  // namespace
 
-void launch_psi6_tiled(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                       void *work, hipStream_t st) {
+void launch_psi6_tiled(const MeasureView &m, uint32_t h, float *re, float *im, float *sre, float *sim,
+                       uint32_t *fail, void *work, hipStream_t st) {
     const uint32_t G = psi6_grid(m);
     double2 *part = static_cast<double2 *>(work);
-    launch_psi6_tile(m, h, re, im, fail, part, nullptr, G, st);
+    launch_psi6_tile(m, h, re, im, sre, sim, fail, part, nullptr, G, st);
     k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
 }
 
@@ -500,18 +535,19 @@ void launch_psi6_tiled(const MeasureView &m, uint32_t h, float *re, float *im, u
 // search fell short for some disk (flag short1, which the caller has
 // cleared), decided on the device.  fail receives the second pass's verdict.
 void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re, float *im,
-                       uint32_t *short1, uint32_t *fail, void *work, hipStream_t st) {
+                       float *sre, float *sim, uint32_t *short1, uint32_t *fail, void *work,
+                       hipStream_t st) {
     const uint32_t G = psi6_grid(m);
     double2 *part = static_cast<double2 *>(work);
-    launch_psi6_tile(m, h1, re, im, short1, part, nullptr, G, st);
-    launch_psi6_tile(m, h2, re, im, fail, part, short1, G, st);
+    launch_psi6_tile(m, h1, re, im, sre, sim, short1, part, nullptr, G, st);
+    launch_psi6_tile(m, h2, re, im, sre, sim, fail, part, short1, G, st);
     k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
 }
 
-void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 const uint32_t *loc, void *work, hipStream_t st) {
+void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, float *sre, float *sim,
+                 uint32_t *fail, const uint32_t *loc, void *work, hipStream_t st) {
     if (measure_tiled(m, h)) {
-        launch_psi6_tiled(m, h, re, im, fail, work, st);
+        launch_psi6_tiled(m, h, re, im, sre, sim, fail, work, st);
         return;
     }
     k_psi6<<<(m.N + 255) / 256, 256, 0, st>>>(m, (int)h, re, im, fail, loc);
@@ -544,6 +580,37 @@ void launch_psi6_field(const MeasureView &m, const float *re, const float *im, f
                        float *fim, hipStream_t st) {
     const uint32_t nc = m.M * m.M;
     k_psi6_field<<<(nc + 255) / 256, 256, 0, st>>>(m, re, im, fre, fim);
+}
+
+// The same field from psi_j stored by cell slot (as the cell lists): the
+// reads follow the cells instead of the tags, and the sums run in the same
+// order, so the result is the same.
+__global__ void __launch_bounds__(256) k_psi6_field_slots(MeasureView m, const float *sre,
+                                                          const float *sim, float *fre, float *fim) {
+    const uint32_t M = m.M, NC = M * M;
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= NC) return;
+    const uint32_t ci = cell % M, cj = cell / M;
+    float sr = 0.0f, si = 0.0f;
+    uint32_t n = 0;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+            const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
+            const uint32_t cnt = m.cnt[nb];
+            for (uint32_t t = 0; t < cnt; ++t) {
+                sr += sre[slot_at(nb, t, NC)];
+                si += sim[slot_at(nb, t, NC)];
+                ++n;
+            }
+        }
+    fre[cell] = n ? sr / (float)n : 0.0f;
+    fim[cell] = n ? si / (float)n : 0.0f;
+}
+
+void launch_psi6_field_slots(const MeasureView &m, const float *sre, const float *sim, float *fre,
+                             float *fim, hipStream_t st) {
+    const uint32_t nc = m.M * m.M;
+    k_psi6_field_slots<<<(nc + 255) / 256, 256, 0, st>>>(m, sre, sim, fre, fim);
 }
 
 // ---------------------------------------------------------------------------

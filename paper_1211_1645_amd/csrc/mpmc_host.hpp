@@ -59,7 +59,8 @@ struct Box {
     float *edges = nullptr;
     uint32_t *scratch_u32 = nullptr;
     void *pos_scratch[2] = {nullptr, nullptr};
-    float *psi_buf = nullptr;  // re[N], im[N], field re/im[M*M]
+    float *psi_buf = nullptr;  // re[N], im[N], field re/im[M*M], by cell slot re/im[CS*M*M]
+    int psi_work();            // allocates psi_buf on first use
     uint32_t *loc = nullptr;   // slot of every disk by tag (measurement kernels)
     int locate();              // fills loc for the current state
     void *meas_work = nullptr;  // partial results of the tiled measurement kernels

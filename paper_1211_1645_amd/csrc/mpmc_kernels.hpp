@@ -80,14 +80,20 @@ size_t measure_work_bytes(uint32_t K);
 void launch_contact_hist(const MeasureView &m, const float *edges, uint32_t K, uint32_t h,
                          unsigned long long *hist, const uint8_t *sel, const uint32_t *loc,
                          void *work, hipStream_t st);
-void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, uint32_t *fail,
-                 const uint32_t *loc, void *work, hipStream_t st);
+// psi_j by tag into re, im; the staged kernels (measure_tiled) also write it
+// by cell slot into sre, sim (CS * M * M each; may be NULL)
+void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, float *sre, float *sim,
+                 uint32_t *fail, const uint32_t *loc, void *work, hipStream_t st);
 // psi6 with stencil h1, then h2 on the device only where h1 fell short (tiled
 // kernels only; h1 < h2).
 void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re, float *im,
-                       uint32_t *short1, uint32_t *fail, void *work, hipStream_t st);
+                       float *sre, float *sim, uint32_t *short1, uint32_t *fail, void *work,
+                       hipStream_t st);
+// the 3 x 3 cell field from psi_j by tag, or (same result) by cell slot
 void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
                        float *fim, hipStream_t st);
+void launch_psi6_field_slots(const MeasureView &m, const float *sre, const float *sim, float *fre,
+                             float *fim, hipStream_t st);
 void launch_validate(const MeasureView &m, uint32_t *tag_seen, hipStream_t st);
 void launch_positions(const MeasureView &m, long long *X, long long *Y, hipStream_t st);
 // out[0..1] = (psi_re, psi_im) / N from the device sums
