@@ -75,11 +75,13 @@ def tune_step(box, target=0.30, rounds=6, block=100):
 
 
 def kernel_source_digest():
-    """Digest of the sources of the timed sweep kernel, to tell whether a
-    stored counter profile still describes it."""
+    """Digest of the sources that define the timed sweep kernel's code (its
+    file and the common header of views, random numbers and constants; the
+    launcher declarations of the other kernels are left out), to tell whether
+    a stored counter profile still describes it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep_fused.hip", "mpmc_common.hpp", "mpmc_kernels.hpp"):
+    for f in ("sweep_fused.hip", "mpmc_common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1211_1645_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -329,8 +329,13 @@ int mpmc_tau(const double *C, uint32_t maxlag, double lo, double hi, double *tau
 /* Sweep schedule of an existing box: MPMC_SCHED_SIMPLE, MPMC_SCHED_FUSED
  * with the given tile side and threads per workgroup (0 = default), or
  * MPMC_SCHED_AUTO (autotune: time every fused shape that fits on this machine's
- * state, keep the fastest; cached per device, M and n_trial).  The state
- * and the trajectory are unaffected.  MPMC_EINVAL if the shape does not fit
+ * state, keep the fastest; cached per device, M and n_trial for the
+ * process, and across processes in the text file named by the environment
+ * variable MPMC_TUNE_CACHE if it is set: one line "<arch> <CUs> <M>
+ * <n_trial> <tile> <threads>" per choice, read before tuning and appended
+ * after; lines whose shape does not fit are ignored, and a file that cannot
+ * be read or written only costs the tuning).  The state and the trajectory
+ * are unaffected.  MPMC_EINVAL if the shape does not fit
  * (fused tiles need cells of at most 4 disks and an even tile <= M). */
 int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t threads);
 

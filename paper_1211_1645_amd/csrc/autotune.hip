@@ -3,7 +3,11 @@
 // own state, or the simple per-colour schedule where tiling does not apply.
 // The trajectory is independent of the choice (counter-keyed random numbers
 // and independent same-colour cells), so tuning can never change results.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
+#include <string>
 #include <vector>
 #include <mutex>
 #include <tuple>
@@ -15,6 +19,55 @@ using namespace mpmc;
 namespace {
 std::mutex g_mu;
 std::map<std::tuple<int, uint32_t, uint32_t>, FusedShape> g_cache;  // (device, M, n_trial)
+
+// The file named by MPMC_TUNE_CACHE, if set, keeps choices across
+// processes: one line per choice, "<arch> <CUs> <M> <n_trial> <tile>
+// <threads>".  A line is used only if its shape is one the library has and
+// fits the box; a tuned choice is appended.
+std::string device_id(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    char buf[300];
+    std::snprintf(buf, sizeof buf, "%s %d", prop.gcnArchName, prop.multiProcessorCount);
+    for (char *c = buf; *c; ++c)
+        if (*c == '\n') *c = ' ';
+    return std::string(buf);
+}
+
+bool file_lookup(const std::string &id, uint32_t M, uint32_t n_trial, const BoxView &v, FusedShape *out) {
+    const char *path = std::getenv("MPMC_TUNE_CACHE");
+    if (!path || !*path || id.empty()) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512], arch[256];
+    bool hit = false;
+    uint32_t n = 0;
+    const FusedShape *shapes = fused_shapes(&n);
+    while (std::fgets(line, sizeof line, f)) {
+        int cus = 0;
+        unsigned m = 0, nt = 0, tile = 0, threads = 0;
+        if (std::sscanf(line, "%255s %d %u %u %u %u", arch, &cus, &m, &nt, &tile, &threads) != 6) continue;
+        char want[300];
+        std::snprintf(want, sizeof want, "%s %d", arch, cus);
+        if (id != want || m != M || nt != n_trial) continue;
+        for (uint32_t i = 0; i < n; ++i)
+            if (shapes[i].tile == tile && shapes[i].threads == threads && fused_supported(v, shapes[i])) {
+                *out = shapes[i];
+                hit = true;  // the last valid line wins
+            }
+    }
+    std::fclose(f);
+    return hit;
+}
+
+void file_store(const std::string &id, uint32_t M, uint32_t n_trial, const FusedShape &s) {
+    const char *path = std::getenv("MPMC_TUNE_CACHE");
+    if (!path || !*path || id.empty()) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;  // the file is a convenience: tuning stands without it
+    std::fprintf(f, "%s %u %u %u %u\n", id.c_str(), M, n_trial, s.tile, s.threads);
+    std::fclose(f);
+}
 }  // namespace
 
 // Times `reps` launches of one shape reading the current buffer and writing
@@ -56,6 +109,12 @@ static int autotune(Box *b, FusedShape *best) {
         auto it = g_cache.find(key);
         if (it != g_cache.end()) { *best = it->second; return MPMC_OK; }
     }
+    const std::string id = device_id(dev);
+    if (file_lookup(id, b->g.M, b->p.n_trial, b->view(b->cur), best)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = *best;
+        return MPMC_OK;
+    }
     int rc = b->materialize();
     if (rc) return rc;
     rc = b->read_scalars();
@@ -88,6 +147,7 @@ static int autotune(Box *b, FusedShape *best) {
     if (!found) return fail(MPMC_EINVAL, "no fused shape fits this box");
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[key] = *best;
+    file_store(id, b->g.M, b->p.n_trial, *best);
     return MPMC_OK;
 }
 

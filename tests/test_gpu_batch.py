@@ -69,3 +69,28 @@ def test_batch_of_64_uneven_boxes(gpu_lib):
         assert same_cells(b, single)
     with pytest.raises(gpu_lib.MPMCError):
         bt.box(0).sweep(1)  # batch members are swept by the batch only
+
+
+def test_autotune_choice_kept_in_file(gpu_lib, tmp_path, monkeypatch):
+    """With MPMC_TUNE_CACHE naming a file, a tuned choice is appended to it,
+    and a line for another grid is taken instead of tuning that grid; the
+    shape never changes the trajectory."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MPMC_TUNE_CACHE", str(path))
+    a = gpu_lib.Box(144 * 144, 0.70, seed=1, step_m=30, n_trial=2)
+    ia = a.info()
+    lines = [l for l in path.read_text().splitlines() if l.strip()]
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert (int(f[2]), int(f[3]), int(f[4])) == (ia["M"], 2, ia["tile"])
+    Mb = gpu_lib.Box(172 * 172, 0.70, seed=1, step_m=30, n_trial=2, schedule="simple").info()["M"]
+    assert Mb != ia["M"]
+    path.write_text(lines[0] + "\n" + "%s %s %d 2 8 64\n" % (f[0], f[1], Mb))
+    b = gpu_lib.Box(172 * 172, 0.70, seed=1, step_m=30, n_trial=2)
+    assert b.info()["tile"] == 8
+    assert len([l for l in path.read_text().splitlines() if l.strip()]) == 2  # nothing tuned
+    c = gpu_lib.Box(172 * 172, 0.70, seed=1, step_m=30, n_trial=2, schedule="fused", tile=24)
+    b.sweep(10)
+    c.sweep(10)
+    for x, y in zip(b.cells(), c.cells()):
+        assert np.array_equal(x, y)
