@@ -328,3 +328,24 @@ def test_validate_counts_hand_placed_overlaps(gpu_lib):
     o.set_positions_q(X, Y)
     assert o.count_overlaps() == 0
     assert g.validate() == (0, 0)
+
+
+def test_zero_length_calls_leave_the_state_alone(gpu_lib):
+    """Empty requests: zero sweeps (plain and learned), zero wave vectors and
+    zero contact accumulations leave the cell lists, the counters and the
+    sweep index as they were."""
+    g = gpu_lib.Box(4096, 0.70, seed=3, step_m=40, cell_min=3.0, schedule="simple")
+    g.sweep(3)
+    before = [c.copy() for c in g.cells()]
+    i0 = g.info()
+    assert g.sweep(0, counts=True) == (0, 0)
+    L = gpu_lib.Learner(seed=1, capacity=16)
+    assert gpu_lib.sweep_learned(g, L, 0, eps=0.1, counts=True) == (0, 0)
+    assert len(g.structure_factor(np.zeros((0, 2), np.int32))) == 0
+    i1 = g.info()
+    for k in ("sweep", "trials", "accepts"):
+        assert i1[k] == i0[k]
+    for a, b in zip(before, g.cells()):
+        assert np.array_equal(a, b)
+    c, n = g.contacts()
+    assert n == 0 and not c.any()
