@@ -330,19 +330,24 @@ int Box::measure_async(double *Psi_dev, bool field) {
     HIPCHK(hipEventRecord(ev_swept, stream));
     HIPCHK(hipStreamWaitEvent(meas_stream, ev_swept, 0));
     const MeasureView m = mview();
-    launch_contact_hist(m, edges, K, hc, hist, nullptr, loc, meas_work, meas_stream);
-    HIPCHK(hipGetLastError());
-    ++n_conf;
     float *dre = psi_buf, *dim = dre + N, *dfr = dim + N, *dfi = dfr + nc;
     float *dsr = dfi + nc, *dsi = dsr + nc * g.CS;
-    if (h1 < hp) {
-        HIPCHK(hipMemsetAsync(async_fail + 1, 0, 4, meas_stream));
-        launch_psi6_retry(m, h1, hp, dre, dim, dsr, dsi, async_fail + 1, async_fail, meas_work,
-                          meas_stream);
+    if (h1 < hp) HIPCHK(hipMemsetAsync(async_fail + 1, 0, 4, meas_stream));
+    if (hc <= h1) {
+        // one staged scan for the contacts and the first psi_6 pass
+        launch_measure_tiled(m, h1, hp, edges, K, hist, dre, dim, dsr, dsi, async_fail + 1,
+                             async_fail, meas_work, meas_stream);
     } else {
-        launch_psi6(m, hp, dre, dim, dsr, dsi, async_fail, loc, meas_work, meas_stream);
+        launch_contact_hist(m, edges, K, hc, hist, nullptr, loc, meas_work, meas_stream);
+        HIPCHK(hipGetLastError());
+        if (h1 < hp)
+            launch_psi6_retry(m, h1, hp, dre, dim, dsr, dsi, async_fail + 1, async_fail, meas_work,
+                              meas_stream);
+        else
+            launch_psi6(m, hp, dre, dim, dsr, dsi, async_fail, loc, meas_work, meas_stream);
     }
     HIPCHK(hipGetLastError());
+    ++n_conf;
     if (field) {  // the staged kernels ran (checked above): psi_j by cell slot is there
         launch_psi6_field_slots(m, dsr, dsi, dfr, dfi, meas_stream);
         HIPCHK(hipGetLastError());

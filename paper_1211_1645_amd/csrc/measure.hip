@@ -89,7 +89,7 @@ struct Stage {
     uint32_t wsum[4], wbig[4];
 };
 
-size_t measure_work_bytes(uint32_t K) { return (size_t)kMeasGrid * (K * 4 + sizeof(double2)); }
+size_t measure_work_bytes(uint32_t K) { return (size_t)kMeasGrid * (K * 4 + sizeof(double2)) + 16; }
 
 bool measure_tiled(const MeasureView &m, uint32_t h) {
     return m.cap <= 4 && h >= 1 && h <= (uint32_t)kStageHalo;
@@ -169,6 +169,16 @@ __device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t
     return (int)all;
 }
 
+// Bin of a pair with E[0] <= r2 < E[K]: start from the square-root estimate,
+// then settle on the exact fp32 edges.
+__device__ __forceinline__ int contact_bin(float r2, const float *E, uint32_t K, float eK) {
+    int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
+    k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
+    while (k > 0 && r2 < E[k]) --k;
+    while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
+    return k;
+}
+
 // Ordered contact pairs of the listed disks into the LDS bins.
 template <int H, int SL>
 __device__ void contact_disks(const Stage &S, const MeasureView &m, const float *E,
@@ -195,13 +205,7 @@ __device__ void contact_disks(const Stage &S, const MeasureView &m, const float 
                     const float r2 = r2_f32(dx, dy);
                     const bool self = di == 0 && dj == 0 && q == s;
                     if (self || !(r2 >= e0) || !(r2 < eK)) continue;
-                    // start from the square-root estimate, then settle on
-                    // the exact fp32 edges
-                    int k = (int)((sqrtf(r2) - 2.0f) * (float)K / (sqrtf(eK) - 2.0f));
-                    k = k < 0 ? 0 : (k >= (int)K ? (int)K - 1 : k);
-                    while (k > 0 && r2 < E[k]) --k;
-                    while (k + 1 < (int)K && !(r2 < E[k + 1])) ++k;
-                    atomicAdd(&bins[k], 1u);
+                    atomicAdd(&bins[contact_bin(r2, E, K, eK)], 1u);
                 }
             }
     }
@@ -379,12 +383,14 @@ __global__ void __launch_bounds__(256) k_psi6(MeasureView m, int h, float *re, f
 // neighbours' offsets are recomputed from their places at the end, in the
 // same arithmetic.  Empty slots hold a far sentinel: they enter only a list
 // that then fails the reach test.  sre, sim (may be NULL) receive psi_j by
-// cell slot as well.
-template <int H, int SL>
+// cell slot as well.  With CT the same scan also bins the ordered contact
+// pairs (squared edges E[0..K] and bins in LDS), as contact_disks does.
+template <int H, int SL, bool CT>
 __device__ void psi6_disks(const Stage &S, const MeasureView &m, uint32_t I0, uint32_t J0, int ndisk,
                            float *re, float *im, float *sre, float *sim, uint32_t *fail, double &pr,
-                           double &pi) {
+                           double &pi, const float *E, uint32_t K, uint32_t *bins) {
     constexpr int SR = kPT + 2 * H;
+    const float e0 = CT ? E[0] : 0.0f, eK = CT ? E[K] : 0.0f;
     for (int j = threadIdx.x; j < ndisk; j += blockDim.x) {
         const uint32_t d = S.disk[j];
         const int cl = (int)(d >> 2), s = (int)(d & 3u);
@@ -410,9 +416,11 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, uint32_t I0, ui
                 for (int q = 0; q < SL; ++q) {
                     const float dx = (comp4f(qx, q) - xi) + cwx;
                     const float dy = (comp4f(qy, q) - yi) + cwy;
+                    const float r2 = r2_f32(dx, dy);
                     const unsigned long long k =
-                        ((unsigned long long)__float_as_uint(r2_f32(dx, dy)) << 32) | comp4u(qt, q);
+                        ((unsigned long long)__float_as_uint(r2) << 32) | comp4u(qt, q);
                     const bool self = di == 0 && dj == 0 && q == s;
+                    if (CT && !self && r2 >= e0 && r2 < eK) atomicAdd(&bins[contact_bin(r2, E, K, eK)], 1u);
                     if (self || !(k < key[5])) continue;
                     key[5] = k;
                     at[5] = ((uint32_t)ne << 2) | (uint32_t)q;
@@ -460,23 +468,36 @@ __device__ void psi6_disks(const Stage &S, const MeasureView &m, uint32_t I0, ui
 // gate: NULL, or a flag that a narrower pass set when its search fell short;
 // with the flag clear the launch does nothing and leaves that pass's psi_j
 // and partials in place.
-template <int H>
+// With CT the workgroup also counts the ordered contact pairs (squared edges
+// E[0..K] from global memory; dynamic LDS of K bins and K + 1 edges) and
+// leaves its row of counts in rows, as k_contact_hist_tile does: one staging
+// of each block serves both measurements.
+template <int H, bool CT>
 __global__ void __launch_bounds__(256) k_psi6_tile(MeasureView m, float *re, float *im, float *sre,
                                                    float *sim, uint32_t *fail, double2 *part,
-                                                   const uint32_t *gate) {
+                                                   const uint32_t *gate, const float *__restrict__ E,
+                                                   uint32_t K, uint32_t *rows) {
     if (gate != nullptr && *gate == 0u) return;  // uniform over the grid
     __shared__ Stage S;
     __shared__ double2 wpart[4];
+    extern __shared__ uint32_t bins[];
+    float *El = reinterpret_cast<float *>(bins + K);
+    if (CT) {
+        for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) bins[k] = 0;
+        for (uint32_t k = threadIdx.x; k <= K; k += blockDim.x) El[k] = E[k];
+    }
     const uint32_t M = m.M, nbx = (M + kPT - 1) / kPT;
     double pr = 0.0, pi = 0.0;
     for (uint32_t blk = blockIdx.x; blk < nbx * nbx; blk += gridDim.x) {
         bool big;
         const uint32_t I0 = (blk % nbx) * kPT, J0 = (blk / nbx) * kPT;
         const int nd = stage_block<H>(S, m, I0, J0, &big);
-        if (big) psi6_disks<H, 4>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi);
-        else psi6_disks<H, 2>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi);
+        if (big) psi6_disks<H, 4, CT>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi, El, K, bins);
+        else psi6_disks<H, 2, CT>(S, m, I0, J0, nd, re, im, sre, sim, fail, pr, pi, El, K, bins);
         __syncthreads();  // S is restaged for the next block
     }
+    if (CT)
+        for (uint32_t k = threadIdx.x; k < K; k += blockDim.x) rows[blockIdx.x * K + k] = bins[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         pr += __shfl_xor(pr, off, 64);
@@ -513,9 +534,18 @@ __global__ void __launch_bounds__(256) k_psi_reduce(const double2 *part, uint32_
 namespace {
 void launch_psi6_tile(const MeasureView &m, uint32_t h, float *re, float *im, float *sre, float *sim,
                       uint32_t *fail, double2 *part, const uint32_t *gate, uint32_t G, hipStream_t st) {
-    if (h == 1) k_psi6_tile<1><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
-    else if (h == 2) k_psi6_tile<2><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
-    else k_psi6_tile<3><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate);
+    if (h == 1) k_psi6_tile<1, false><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate, nullptr, 0, nullptr);
+    else if (h == 2) k_psi6_tile<2, false><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate, nullptr, 0, nullptr);
+    else k_psi6_tile<3, false><<<G, 256, 0, st>>>(m, re, im, sre, sim, fail, part, gate, nullptr, 0, nullptr);
+}
+// The same pass also counting contacts into rows (G rows of K).
+void launch_psi6_contact_tile(const MeasureView &m, uint32_t h, float *re, float *im, float *sre,
+                              float *sim, uint32_t *fail, double2 *part, const float *E, uint32_t K,
+                              uint32_t *rows, uint32_t G, hipStream_t st) {
+    const size_t lds = (2 * (size_t)K + 1) * sizeof(uint32_t);
+    if (h == 1) k_psi6_tile<1, true><<<G, 256, lds, st>>>(m, re, im, sre, sim, fail, part, nullptr, E, K, rows);
+    else if (h == 2) k_psi6_tile<2, true><<<G, 256, lds, st>>>(m, re, im, sre, sim, fail, part, nullptr, E, K, rows);
+    else k_psi6_tile<3, true><<<G, 256, lds, st>>>(m, re, im, sre, sim, fail, part, nullptr, E, K, rows);
 }
 uint32_t psi6_grid(const MeasureView &m) {
     const uint32_t nb = (m.M + kPT - 1) / kPT;
@@ -541,6 +571,19 @@ void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re
     double2 *part = static_cast<double2 *>(work);
     launch_psi6_tile(m, h1, re, im, sre, sim, short1, part, nullptr, G, st);
     launch_psi6_tile(m, h2, re, im, sre, sim, fail, part, short1, G, st);
+    k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
+}
+
+void launch_measure_tiled(const MeasureView &m, uint32_t h1, uint32_t h2, const float *edges,
+                          uint32_t K, unsigned long long *hist, float *re, float *im, float *sre,
+                          float *sim, uint32_t *short1, uint32_t *fail, void *work, hipStream_t st) {
+    const uint32_t G = psi6_grid(m);
+    uint32_t *rows = static_cast<uint32_t *>(work);
+    const size_t off = ((size_t)G * K * sizeof(uint32_t) + 15) & ~(size_t)15;
+    double2 *part = reinterpret_cast<double2 *>(static_cast<char *>(work) + off);
+    launch_psi6_contact_tile(m, h1, re, im, sre, sim, h2 > h1 ? short1 : fail, part, edges, K, rows, G, st);
+    k_hist_rows_reduce<<<K, 256, 0, st>>>(rows, G, K, hist);
+    if (h2 > h1) launch_psi6_tile(m, h2, re, im, sre, sim, fail, part, short1, G, st);
     k_psi_reduce<<<1, 256, 0, st>>>(part, G, m.dev);
 }
 

@@ -89,6 +89,14 @@ void launch_psi6(const MeasureView &m, uint32_t h, float *re, float *im, float *
 void launch_psi6_retry(const MeasureView &m, uint32_t h1, uint32_t h2, float *re, float *im,
                        float *sre, float *sim, uint32_t *short1, uint32_t *fail, void *work,
                        hipStream_t st);
+// The asynchronous measurement's staged pass: the contact histogram (into
+// hist, exact for any stencil h1 >= the one the histogram range needs) and
+// psi_j with stencil h1 in one scan; then psi_j with h2 > h1 on the device
+// only where h1 fell short (flag short1, cleared by the caller; h2 == h1:
+// no second pass, and fail takes the first pass's verdict).
+void launch_measure_tiled(const MeasureView &m, uint32_t h1, uint32_t h2, const float *edges,
+                          uint32_t K, unsigned long long *hist, float *re, float *im, float *sre,
+                          float *sim, uint32_t *short1, uint32_t *fail, void *work, hipStream_t st);
 // the 3 x 3 cell field from psi_j by tag, or (same result) by cell slot
 void launch_psi6_field(const MeasureView &m, const float *re, const float *im, float *fre,
                        float *fim, hipStream_t st);

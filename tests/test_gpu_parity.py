@@ -349,3 +349,27 @@ def test_zero_length_calls_leave_the_state_alone(gpu_lib):
         assert np.array_equal(a, b)
     c, n = g.contacts()
     assert n == 0 and not c.any()
+
+
+def test_upload_rejects_a_cell_beyond_capacity(gpu_lib):
+    """More disks in one cell than its width can hold without overlap (the
+    capacity the geometry derives) is refused on upload with MPMC_EOVERFLOW,
+    before any kernel sees it, and the box keeps its state."""
+    Q22 = 2 ** 22
+    g = gpu_lib.Box(16, 0.008, seed=1, lattice="none", schedule="simple")
+    info = g.info()
+    cap, W, M = info["cap"], info["W"], info["M"]
+    X = np.array([(10 + 4 * (k % 4)) * Q22 for k in range(16)], np.int64)
+    Y = np.array([(10 + 4 * (k // 4)) * Q22 for k in range(16)], np.int64)
+    g.set_positions_q(X, Y)
+    before = [c.copy() for c in g.cells()]
+    # cap + 1 disks spread inside cell (1, 1)
+    for k in range(cap + 1):
+        X[k] = W + (k * W) // (cap + 2)
+        Y[k] = W + W // 2
+    with pytest.raises(gpu_lib.MPMCError) as e:
+        g.set_positions_q(X, Y)
+    assert e.value.code == gpu_lib.EOVERFLOW
+    for a, b in zip(before, g.cells()):
+        assert np.array_equal(a, b)
+    assert M > 2
