@@ -107,23 +107,46 @@ __device__ __forceinline__ uint32_t comp4u(const uint4 &v, int s) {
 // disks; *big tells whether some staged cell holds more than two.
 template <int H>
 __device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t J0, bool *big) {
-    constexpr int SR = kPT + 2 * H;
+    constexpr int SR = kPT + 2 * H, NS = SR * SR, NIT = (NS + 255) / 256;
     const uint32_t M = m.M, NC = M * M;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    bool crowded = false;
-    for (int e = threadIdx.x; e < SR * SR; e += blockDim.x) {
-        const int rx = e % SR, ry = e / SR;
+    // this thread's own cell (for the list of the block's disks), then the
+    // counts and slots 0, 1 of every staged cell: all in one round trip, the
+    // loads issued at raised priority so that they leave before the other
+    // waves' arithmetic (unused slots hold stale values and are replaced by
+    // the sentinel); slots 2, 3 afterwards where the count asks for them
+    const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT;
+    const bool inb = I0 + tx < M && J0 + ty < M;
+    uint32_t nown = 0;
+    __builtin_amdgcn_s_setprio(3);
+    if (inb) nown = m.cnt[wrapc((int)I0 + tx, M) + M * wrapc((int)J0 + ty, M)];
+    uint32_t c_r[NIT], n_r[NIT], ta[NIT], tb[NIT];
+    float xa[NIT], xb[NIT], ya[NIT], yb[NIT];
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int e = (int)threadIdx.x + 256 * i, ee = e < NS ? e : 0;
+        const int rx = ee % SR, ry = ee / SR;
         const uint32_t c = wrapc((int)I0 - H + rx, M) + M * wrapc((int)J0 - H + ry, M);
-        // count and slots 0, 1 in one round trip (unused slots hold stale
-        // values and are replaced by the sentinel); slots 2, 3 where needed
-        uint32_t n = m.cnt[c];
-        const float xa = m.x[c], xb = m.x[NC + c], ya = m.y[c], yb = m.y[NC + c];
-        const uint32_t ta = m.tag[c], tb = m.tag[NC + c];
-        n = n > 4 ? 4 : n;
+        c_r[i] = c;
+        n_r[i] = m.cnt[c];
+        xa[i] = m.x[c];
+        xb[i] = m.x[NC + c];
+        ya[i] = m.y[c];
+        yb[i] = m.y[NC + c];
+        ta[i] = m.tag[c];
+        tb[i] = m.tag[NC + c];
+    }
+    __builtin_amdgcn_s_setprio(0);
+    bool crowded = false;
+#pragma unroll
+    for (int i = 0; i < NIT; ++i) {
+        const int e = (int)threadIdx.x + 256 * i;
+        if (e >= NS) break;
+        const uint32_t c = c_r[i], n = n_r[i] > 4 ? 4 : n_r[i];
         float4 x4 = make_float4(kFarM, kFarM, kFarM, kFarM), y4 = x4;
         uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
-        if (n > 0) { x4.x = xa; y4.x = ya; t4.x = ta; }
-        if (n > 1) { x4.y = xb; y4.y = yb; t4.y = tb; }
+        if (n > 0) { x4.x = xa[i]; y4.x = ya[i]; t4.x = ta[i]; }
+        if (n > 1) { x4.y = xb[i]; y4.y = yb[i]; t4.y = tb[i]; }
         if (n > 2) { x4.z = m.x[2 * NC + c]; y4.z = m.y[2 * NC + c]; t4.z = m.tag[2 * NC + c]; }
         if (n > 3) { x4.w = m.x[3 * NC + c]; y4.w = m.y[3 * NC + c]; t4.w = m.tag[3 * NC + c]; }
         S.x[e] = x4;
@@ -132,16 +155,9 @@ __device__ int stage_block(Stage &S, const MeasureView &m, uint32_t I0, uint32_t
         S.cnt[e] = (uint8_t)n;
         crowded |= n > 2;
     }
-    // this thread's own cell and its disk count; prefix sums over the block
-    // from bit-plane ballots (a count is below 8)
-    const int tx = threadIdx.x % kPT, ty = threadIdx.x / kPT;
-    const bool inb = I0 + tx < M && J0 + ty < M;
-    uint32_t nown = 0;
-    if (inb) {
-        const uint32_t c = wrapc((int)I0 + tx, M) + M * wrapc((int)J0 + ty, M);
-        nown = m.cnt[c];
-        nown = nown > 4 ? 4 : nown;
-    }
+    // prefix sums of the own counts over the block from bit-plane ballots (a
+    // count is below 8)
+    nown = nown > 4 ? 4 : nown;
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t pre = 0, tot = 0;
 #pragma unroll
@@ -628,24 +644,40 @@ void launch_psi6_field(const MeasureView &m, const float *re, const float *im, f
 // The same field from psi_j stored by cell slot (as the cell lists): the
 // reads follow the cells instead of the tags, and the sums run in the same
 // order, so the result is the same.
+// The loads go out in two rounds (the nine counts, then the values of the
+// slots they cover, at most 4 per cell here) and the sums run afterwards in
+// the cell-then-slot order of k_psi6_field.
 __global__ void __launch_bounds__(256) k_psi6_field_slots(MeasureView m, const float *sre,
                                                           const float *sim, float *fre, float *fim) {
     const uint32_t M = m.M, NC = M * M;
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= NC) return;
     const uint32_t ci = cell % M, cj = cell / M;
+    uint32_t nb[9], cnt[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        nb[k] = wrapc((int)ci + k % 3 - 1, M) + M * wrapc((int)cj + k / 3 - 1, M);
+        cnt[k] = m.cnt[nb[k]];
+    }
+    float vr[9][4], vi[9][4];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            vr[k][t] = (uint32_t)t < cnt[k] ? sre[slot_at(nb[k], (uint32_t)t, NC)] : 0.0f;
+            vi[k][t] = (uint32_t)t < cnt[k] ? sim[slot_at(nb[k], (uint32_t)t, NC)] : 0.0f;
+        }
     float sr = 0.0f, si = 0.0f;
     uint32_t n = 0;
-    for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-            const uint32_t nb = wrapc((int)ci + di, M) + M * wrapc((int)cj + dj, M);
-            const uint32_t cnt = m.cnt[nb];
-            for (uint32_t t = 0; t < cnt; ++t) {
-                sr += sre[slot_at(nb, t, NC)];
-                si += sim[slot_at(nb, t, NC)];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if ((uint32_t)t < cnt[k]) {
+                sr += vr[k][t];
+                si += vi[k][t];
                 ++n;
             }
-        }
     fre[cell] = n ? sr / (float)n : 0.0f;
     fim[cell] = n ? si / (float)n : 0.0f;
 }
