@@ -450,6 +450,12 @@ int mpmc_learner_info(mpmc_learner l, uint64_t *n_data, uint64_t *n_feature_over
 /* Features of the disks with the given tags at their current positions,
  * F[n][24] (host). */
 int mpmc_learned_features(mpmc_box b, const uint32_t *tags, uint32_t n, float *F);
+/* Active cells per wave of the learned colour pass: 16, 32 or 64, or 0
+ * (the default) to choose from the box size: the smallest of 16 and 32 that
+ * needs no more waves than the device has SIMDs, else 64 (a wave's network
+ * work shrinks with its cells, and small boxes then use more SIMDs).  The
+ * trajectory is the same for every value.  MPMC_EINVAL for other values. */
+int mpmc_set_learned_cells_per_wave(mpmc_box b, uint32_t cells);
 /* k sweeps with the learned proposal (eps in [0, 1] is the weight of the
  * uniform fallback); counts as mpmc_sweep. */
 int mpmc_sweep_learned(mpmc_box b, mpmc_learner l, uint64_t k, float eps, uint64_t *trials,

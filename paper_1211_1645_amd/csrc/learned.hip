@@ -210,10 +210,10 @@ __device__ inline v4s act_bf16(v4f c, const float *bias, int n0) {
     return __builtin_bit_cast(v4s, h);
 }
 
-__device__ inline void mlp_infer_wave(const InferW &W, const uint16_t *X, float *OUT) {
+__device__ inline void mlp_infer_wave(const InferW &W, const uint16_t *X, float *OUT, int nblk = 4) {
     const int l = threadIdx.x & 63, r = l & 15, kg = (l >> 4) * 4;
 #pragma unroll 1
-    for (int mt = 0; mt < 4; ++mt) {
+    for (int mt = 0; mt < nblk; ++mt) {
         v4f c1[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) c1[nt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -606,6 +606,7 @@ struct LearnView {
     double e;                        // its probability, E / 2^32
     unsigned long long *nfeat_over;  // neighbourhoods with more than 12 disks
     unsigned long long *stamps;      // phase profile (NULL normally): kLearnStamps per wave
+    uint32_t cpw;                    // active cells per wave: 16, 32 or 64
 };
 
 // Phase profile of the learned pass: lane 0 of each wave records the device
@@ -668,11 +669,15 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
     // the barrier that completes it comes just before the first network
     load_infer_weights(L.w, lv.W, threadIdx.x, 64 * kLearnWaves);
     const uint32_t M = v.M, h = M / 2;
-    const uint32_t t = blockIdx.x * (64 * kLearnWaves) + threadIdx.x;
+    // wave w of the grid takes active cells w cpw .. w cpw + cpw - 1, one per
+    // lane; lanes from cpw on have no cell, and the network runs on cpw / 16
+    // blocks of 16 rows
+    const uint32_t t = (blockIdx.x * kLearnWaves + (threadIdx.x >> 6)) * lv.cpw + (uint32_t)lane;
+    const int nblk = (int)(lv.cpw >> 4);
     const uint64_t sweep = v.dev->sweep + v.offset;
     const SweepDraws sd = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
     const uint32_t colour = colour_of_pass(sd.perm, pass);
-    const bool valid = t < h * h;
+    const bool valid = (uint32_t)lane < lv.cpw && t < h * h;
     const uint32_t ci = valid ? 2 * (t % h) + (colour & 1u) : 0;
     const uint32_t cj = valid ? 2 * (t / h) + (colour >> 1) : 0;
     const uint32_t cell = ci + M * cj;
@@ -735,7 +740,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         learn_stamp(lv, lane, tr, 2);
         if (tr == 0) __syncthreads();  // the weights are in LDS
         float *OUT = P.so;
-        mlp_infer_wave(L.w, P.X, OUT);
+        mlp_infer_wave(L.w, P.X, OUT, nblk);
         learn_stamp(lv, lane, tr, 3);
         // propose D from the lattice law and keep P(D)
         int Dx = 0, Dy = 0;
@@ -767,7 +772,7 @@ __global__ void __launch_bounds__(64 * kLearnWaves) k_pass_learned(BoxView v, ui
         }
         wave_sync();
         learn_stamp(lv, lane, tr, 6);
-        mlp_infer_wave(L.w, P.X, OUT);
+        mlp_infer_wave(L.w, P.X, OUT, nblk);
         learn_stamp(lv, lane, tr, 7);
         if (act) ++trials;
         if (ok) {
@@ -1459,6 +1464,32 @@ extern "C" int mpmc_learned_features(mpmc_box bh, const uint32_t *tags, uint32_t
 // update per sweep.  With `stamps` (room for the waves of one pass) each
 // sweep is synchronised and the phase durations of every wave of every pass
 // are added to phase_ticks[kLearnStamps - 1].
+// Active cells per wave of the learned pass.  A wave's time is mostly the
+// latency of its per-lane work (one wave runs per SIMD), and its network
+// part shrinks with the rows it holds, so a pass that would not give every
+// SIMD a wave of 64 cells spreads its cells over more waves of 16 or 32:
+// the smallest of 16, 32 that needs no more waves than the GPU has SIMDs,
+// else 64.  A box's own setting (mpmc_set_learned_cells_per_wave) wins.
+// The trajectory does not depend on it: random numbers are keyed by cell,
+// and each network row is computed on its own.
+static uint32_t learned_cells_per_wave(const Box *b, uint32_t na) {
+    if (b->learned_cpw) return b->learned_cpw;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    const uint32_t simds = 4u * (uint32_t)cus;
+    for (uint32_t c = 16; c < 64; c *= 2)
+        if ((na + c - 1) / c <= simds) return c;
+    return 64;
+}
+
+// Workgroups of kLearnWaves waves for na active cells at cpw cells per wave.
+static uint32_t learned_grid(uint32_t na, uint32_t cpw) {
+    const uint32_t waves = (na + cpw - 1) / cpw;
+    return (waves + kLearnWaves - 1) / kLearnWaves;
+}
+
 // A run of learned sweeps replays a captured graph of this many sweeps (even:
 // the double-buffered lists return to the buffer they started in) while the
 // box uses graphs; shorter remainders are launched one sweep at a time.
@@ -1483,7 +1514,7 @@ static void launch_learned_sweep(Box *b, int from, uint32_t j, const LearnView &
 // threshold differs from the last capture.
 static int learned_graph(Box *b, const LearnView &lv, uint32_t grid, size_t lds) {
     if (b->lgraph_exec && b->lgraph_W == (const void *)lv.W && b->lgraph_over == (const void *)lv.nfeat_over &&
-        b->lgraph_E == lv.E)
+        b->lgraph_E == lv.E && b->lgraph_cpw == lv.cpw)
         return MPMC_OK;
     if (b->lgraph_exec) (void)hipGraphExecDestroy(b->lgraph_exec);
     b->lgraph_exec = nullptr;
@@ -1503,6 +1534,7 @@ static int learned_graph(Box *b, const LearnView &lv, uint32_t grid, size_t lds)
     b->lgraph_W = lv.W;
     b->lgraph_over = lv.nfeat_over;
     b->lgraph_E = lv.E;
+    b->lgraph_cpw = lv.cpw;
     return MPMC_OK;
 }
 
@@ -1518,8 +1550,9 @@ static int learned_sweeps(Box *b, Learner *l, uint64_t k, float eps, unsigned lo
     const uint64_t E = branch_threshold(eps);
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
     constexpr uint32_t nt = 64 * kLearnWaves;
-    const uint32_t grid = (na + nt - 1) / nt, waves = grid * kLearnWaves;
-    const LearnView lv{l->W, E, ldexp((double)E, -32), l->over, stamps};
+    const uint32_t cpw = learned_cells_per_wave(b, na);
+    const uint32_t grid = learned_grid(na, cpw), waves = grid * kLearnWaves;
+    const LearnView lv{l->W, E, ldexp((double)E, -32), l->over, stamps, cpw};
     std::vector<unsigned long long> h(stamps ? (size_t)waves * kLearnStamps : 0);
     for (uint64_t s = 0; s < k;) {
         if (!stamps && b->use_graphs && b->cur == 0 && k - s >= kLearnGraphSweeps) {
@@ -1592,7 +1625,7 @@ extern "C" int mpmc_profile_learned(mpmc_box bh, mpmc_learner lh, uint32_t sweep
     int rc = check_learned_box(b);
     if (rc) return rc;
     const uint32_t na = (b->g.M / 2) * (b->g.M / 2);
-    const uint32_t waves = (na + 64 * kLearnWaves - 1) / (64 * kLearnWaves) * kLearnWaves;
+    const uint32_t waves = learned_grid(na, learned_cells_per_wave(b, na)) * kLearnWaves;
     unsigned long long *d = nullptr;
     rc = b->alloc_dev((void **)&d, (size_t)waves * kLearnStamps * 8);
     if (rc) return rc;
@@ -1606,6 +1639,14 @@ extern "C" int mpmc_profile_learned(mpmc_box bh, mpmc_learner lh, uint32_t sweep
     const double us_per_tick = 1e3 / (double)(khz > 0 ? khz : 100000);
     for (int ph = 0; ph + 1 < kLearnStamps; ++ph)
         phase_us[ph] = ticks[ph] / ((double)waves * 4 * sweeps) * us_per_tick;
+    return MPMC_OK;
+}
+
+extern "C" int mpmc_set_learned_cells_per_wave(mpmc_box bh, uint32_t cells) {
+    if (!bh) return fail(MPMC_EINVAL, "NULL box");
+    if (cells != 0 && cells != 16 && cells != 32 && cells != 64)
+        return fail(MPMC_EINVAL, "cells per wave must be 0 (automatic), 16, 32 or 64");
+    BX(bh)->learned_cpw = cells;
     return MPMC_OK;
 }
 

@@ -85,6 +85,8 @@ struct Box {
     hipGraphExec_t lgraph_exec = nullptr;
     const void *lgraph_W = nullptr, *lgraph_over = nullptr;
     uint64_t lgraph_E = 0;
+    uint32_t lgraph_cpw = 0;
+    uint32_t learned_cpw = 0;  // active cells per wave of the learned pass; 0: automatic
     // Asynchronous measurement: its kernels run on meas_stream and read only
     // the canonical buffers C; every later write of C, and every other use of
     // the measurement buffers, first waits for ev_meas on the box's stream.

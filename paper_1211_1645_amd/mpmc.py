@@ -93,6 +93,7 @@ _SIGS = {
                  C.POINTER(C.c_double)],
     "mpmc_set_schedule": [_P, C.c_uint32, C.c_uint32, C.c_uint32],
     "mpmc_set_graphs": [_P, C.c_uint32],
+    "mpmc_set_learned_cells_per_wave": [_P, C.c_uint32],
     "mpmc_profile_phases": [_P, C.c_uint32, _P],
     "mpmc_batch_create": [C.POINTER(C.c_void_p), C.c_uint32, _P, _P, _P, C.POINTER(Params)],
     "mpmc_batch_free": [_P],
@@ -271,6 +272,10 @@ class Box:
 
     def set_graphs(self, sweeps_per_graph):
         _check(_lib.mpmc_set_graphs(self.h, sweeps_per_graph))
+
+    def set_learned_cells_per_wave(self, cells):
+        """Active cells per wave of the learned pass (16, 32, 64; 0 = by box size)."""
+        _check(_lib.mpmc_set_learned_cells_per_wave(self.h, cells))
 
     PHASES = ("load", "pass1", "pass2", "pass3", "pass4", "rebin_classes", "rebin_scatter",
               "tile", "entry_to_work", "launch_span", "tiles_in_flight", "last_entry")

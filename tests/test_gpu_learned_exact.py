@@ -214,3 +214,25 @@ def test_learned_graph_replays_match_direct_launches(gpu_lib):
     for x, y in zip(a.cells(), b.cells()):
         assert np.array_equal(x, y)
     assert a.validate() == (0, 0)
+
+
+def test_learned_cells_per_wave_do_not_change_the_trajectory(gpu_lib):
+    """The learned pass spreads a colour's cells over waves of 16, 32 or 64
+    cells; random numbers are keyed by cell and every network row is its own,
+    so the trajectory and the counts are the same for each choice (and for
+    the automatic one)."""
+    L = gpu_lib.Learner(seed=1, capacity=16)
+    L.set_params(inputs.mlp_params(8))
+    runs = []
+    for cells in (0, 16, 32, 64):
+        b = gpu_lib.Box(4096, 0.70, seed=9, step_m=40, cell_min=3.0, schedule="simple")
+        b.set_learned_cells_per_wave(cells)
+        counts = gpu_lib.sweep_learned(b, L, 11, eps=0.2, counts=True)
+        runs.append((counts, [c.copy() for c in b.cells()]))
+    for counts, cells in runs[1:]:
+        assert counts == runs[0][0]
+        for x, y in zip(cells, runs[0][1]):
+            assert np.array_equal(x, y)
+    b = gpu_lib.Box(4096, 0.70, seed=9, step_m=40, cell_min=3.0, schedule="simple")
+    with pytest.raises(gpu_lib.MPMCError):
+        b.set_learned_cells_per_wave(48)
