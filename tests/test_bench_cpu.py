@@ -61,3 +61,45 @@ def test_stored_pressure_agrees_with_table_one():
     assert mean == pytest.approx(p["p_star"], abs=1e-12)
     assert sd / math.sqrt(len(rep)) == pytest.approx(p["se"], rel=1e-9)
     assert abs(p["p_star"] - 9.17078) < 3 * math.hypot(p["se"], 4.5e-5)
+
+
+def test_stored_tau_compare_is_consistent():
+    """The committed learned-against-plain comparison: each rate is the
+    run's sweeps per second over its tau in sweeps, and the reported gains
+    are the ratios of those figures."""
+    import json
+    import os
+    c = bench.stored_tau_compare()
+    assert c is not None and c["provenance"].startswith("stored")
+    assert set(c["decorrelations_per_s"]) == {"plain_w3", "plain_w2_fused", "learned_w3"}
+    d = json.load(open(os.path.join(bench.ROOT, "profiles",
+                                    "psi6_tau_learned_vs_plain_128sq_eta066.json")))
+    s = d["samplers"]
+    for k, v in s.items():
+        assert v["decorrelations_per_s"] == pytest.approx(v["sweeps_per_s"] / v["tau_sweeps"], rel=1e-9)
+        assert c["tau_sweeps"][k] == [v["tau_sweeps"], v["tau_sweeps_se"]]
+    rate = {k: v["decorrelations_per_s"] for k, v in s.items()}
+    assert c["gain_decorrelations_per_s_vs_plain_w3"] == pytest.approx(
+        rate["learned_w3"] / rate["plain_w3"], rel=1e-9)
+    assert c["gain_decorrelations_per_s_vs_plain_w2_fused"] == pytest.approx(
+        rate["learned_w3"] / rate["plain_w2_fused"], rel=1e-9)
+    assert c["gain_tau_per_sweep_vs_plain_w3"] == pytest.approx(
+        s["plain_w3"]["tau_sweeps"] / s["learned_w3"]["tau_sweeps"], rel=1e-9)
+
+
+class _StubBox:
+    def __init__(self, w):
+        self.w = w
+
+    def info(self):
+        return {"w": self.w}
+
+
+def test_max_step_keeps_width_plus_step_below_four():
+    """The step m moves a disk by at most m/256 sigma per coordinate; the
+    largest m the box allows keeps w + m/256 below 4 sigma, capped at 255."""
+    for w in (2.0, 2.5, 3.0, 3.04, 3.5, 3.66, 3.99):
+        m = bench.max_step(_StubBox(w))
+        assert 0 <= m <= 255
+        assert w + m / 256.0 < 4.0
+        assert m == 255 or w + (m + 1) / 256.0 >= 4.0
