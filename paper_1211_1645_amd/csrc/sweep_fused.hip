@@ -58,8 +58,11 @@ namespace {
 constexpr int kHalo = 4;
 constexpr float kFar = 1.0e6f;  // sentinel offset of an empty slot
 
-template <int TILE>
+// Four-slot records: every cell of the region keeps up to four disks.
+template <int TILE_>
 struct Lds {
+    static constexpr int TILE = TILE_;
+    static constexpr bool kTwo = false;
     static constexpr int RL = TILE + 2 * kHalo + 1;  // loaded region side
     static constexpr int R = RL + 1;                 // allocated side (even)
     static constexpr int NC = R * R;
@@ -70,6 +73,29 @@ struct Lds {
     uint16_t gcnt[TE * TE];  // re-bin: per old cell, disks per wrap class, 3 bits each
     uint32_t big;            // some region cell holds more than two disks
 };
+
+// Two-slot records (x0, x1, y0, y1), half the LDS of the four-slot form, so
+// that a larger tile still fits four workgroups per CU.  A region with a
+// cell of more than two disks cannot be held this way: the tile then runs
+// as four-slot sub-tiles instead.
+template <int TILE_>
+struct Lds2 {
+    static constexpr int TILE = TILE_;
+    static constexpr bool kTwo = true;
+    static constexpr int RL = TILE + 2 * kHalo + 1;
+    static constexpr int R = RL + 1;
+    static constexpr int NC = R * R;
+    static constexpr int TE = TILE + 1;
+    float4 xy[NC];
+    uint8_t cnt[NC];
+    uint16_t gcnt[TE * TE];
+    uint32_t big;
+};
+
+// Side of the four-slot sub-tiles that stand in for a two-slot tile of side
+// TILE (two by two of them; even, so that colours keep their parity).
+template <int TILE>
+constexpr int sub_tile() { return ((TILE / 2) + 1) & ~1; }
 
 // LDS index of region cell (rx, ry): colour plane, then row-major in plane.
 template <int R>
@@ -115,6 +141,41 @@ __device__ __forceinline__ float4 put4(float4 v, uint32_t s, float f) {
 }
 __device__ __forceinline__ float comp4(const float4 &v, int s) {
     return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
+// The records of region cell e as four-wide x and y vectors (in the two-slot
+// layout slots 2 and 3 read as the far sentinel), and their write-back.
+template <int T>
+__device__ __forceinline__ void rec_get(const Lds<T> &L, int e, float4 &mx, float4 &my) {
+    mx = L.x[e];
+    my = L.y[e];
+}
+template <int T>
+__device__ __forceinline__ void rec_get(const Lds2<T> &L, int e, float4 &mx, float4 &my) {
+    const float4 r = L.xy[e];
+    mx = make_float4(r.x, r.y, kFar, kFar);
+    my = make_float4(r.z, r.w, kFar, kFar);
+}
+template <int T>
+__device__ __forceinline__ void rec_put(Lds<T> &L, int e, const float4 &mx, const float4 &my) {
+    L.x[e] = mx;
+    L.y[e] = my;
+}
+template <int T>
+__device__ __forceinline__ void rec_put(Lds2<T> &L, int e, const float4 &mx, const float4 &my) {
+    L.xy[e] = make_float4(mx.x, mx.y, my.x, my.y);
+}
+// Slots 0 and 1 of a neighbour cell.
+template <int T>
+__device__ __forceinline__ void rec_get2(const Lds<T> &L, int e, float2 &qx, float2 &qy) {
+    qx = *reinterpret_cast<const float2 *>(&L.x[e]);
+    qy = *reinterpret_cast<const float2 *>(&L.y[e]);
+}
+template <int T>
+__device__ __forceinline__ void rec_get2(const Lds2<T> &L, int e, float2 &qx, float2 &qy) {
+    const float4 r = L.xy[e];
+    qx = make_float2(r.x, r.y);
+    qy = make_float2(r.z, r.w);
 }
 }  // namespace
 
@@ -162,15 +223,15 @@ __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_
             const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
             const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
             const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
-            if (SL > 2) {
+            if constexpr (SL > 2) {
                 const float4 qx = L.x[ne], qy = L.y[ne];
                 bad |= overlap_f32(qx.x - gx, qy.x - gy);
                 bad |= overlap_f32(qx.y - gx, qy.y - gy);
                 bad |= overlap_f32(qx.z - gx, qy.z - gy);
                 bad |= overlap_f32(qx.w - gx, qy.w - gy);
             } else {
-                const float2 qx = *reinterpret_cast<const float2 *>(&L.x[ne]);
-                const float2 qy = *reinterpret_cast<const float2 *>(&L.y[ne]);
+                float2 qx, qy;
+                rec_get2(L, ne, qx, qy);
                 dmin = fminf(dmin, r2_f32(qx.x - gx, qy.x - gy));
                 dmin = fminf(dmin, r2_f32(qx.y - gx, qy.y - gy));
             }
@@ -217,11 +278,11 @@ __device__ __forceinline__ bool try_move(const LdsT &L, int base_ax, uint32_t sl
 // cell of that rectangle of the colour plane; lanes of empty cells idle.
 // (Listing the non-empty cells first saves those lanes but costs a ballot,
 // a scan and two barriers per pass, more than it saves.)
-template <int TILE, int THREADS, int CX, int CY, typename View>
-__device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const PassCtx &ctx,
-                                         int tid, int p, uint32_t &trials, uint32_t &accepts) {
-    constexpr int H = Lds<TILE>::R / 2, PB = (CX | (CY << 1)) * H * H;
-    constexpr int RL = Lds<TILE>::RL;
+template <typename LdsT, int THREADS, int CX, int CY, typename View>
+__device__ __forceinline__ void run_pass(LdsT &L, const View &v, const PassCtx &ctx, int tid,
+                                         int p, uint32_t &trials, uint32_t &accepts) {
+    constexpr int H = LdsT::R / 2, PB = (CX | (CY << 1)) * H * H;
+    constexpr int RL = LdsT::RL;
     const uint32_t M = v.M;
     const float w = v.w, cen = ctx.cen;
     const float lo_b = -cen, hi_b = w - cen;  // in-cell range of centred offsets
@@ -253,7 +314,8 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
             }
         }
         const int base_ax = a;  // ax + H * ay inside a plane
-        float4 mx = L.x[e], my = L.y[e];
+        float4 mx, my;
+        rec_get(L, e, mx, my);
         for (uint32_t t = 0; t < v.n_trial; ++t) {
             const Words w4 = draw(v.seed_lo, v.seed_hi, ctx.sweep, cell, t, kStreamTrial);
             const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n)
@@ -261,13 +323,16 @@ __device__ __forceinline__ void run_pass(Lds<TILE> &L, const View &v, const Pass
             const float dxs = step_from_word(w4.w1, v.step_m);
             const float dys = step_from_word(w4.w2, v.step_m);
             if (own) ++trials;
-            const bool acc =
-                ctx.big ? try_move<4, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w)
-                        : try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
+            bool acc;
+            if constexpr (LdsT::kTwo)
+                acc = try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
+            else
+                acc = ctx.big
+                          ? try_move<4, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w)
+                          : try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
             if (own && acc) ++accepts;
         }
-        L.x[e] = mx;
-        L.y[e] = my;
+        rec_put(L, e, mx, my);
     }
 }
 
@@ -281,16 +346,22 @@ __device__ __forceinline__ void stamp_at(unsigned long long *stamp, int tid, int
 }
 
 // The work of one tile: load, four colour passes, canonical write-back,
-// re-bin into the next sweep's grid, counts.
-template <int TILE, int THREADS, typename View>
-__device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid, uint32_t I0,
-                                           uint32_t J0, unsigned long long *stamp) {
-    constexpr int RL = Lds<TILE>::RL, R = Lds<TILE>::R, TE = Lds<TILE>::TE;
+// re-bin into the next sweep's grid, counts.  The tile owns the cells
+// [I0, I0 + lim_x) x [J0, J0 + lim_y) (lim <= TILE) that lie in the box.
+// In the two-slot layout a region holding a cell of more than two disks
+// makes it return false before it writes anything outside LDS; otherwise
+// it returns true.
+template <typename LdsT, int THREADS, typename View>
+__device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint32_t I0,
+                                           uint32_t J0, int lim_x, int lim_y,
+                                           unsigned long long *stamp) {
+    constexpr bool kTwo = LdsT::kTwo;
+    constexpr int RL = LdsT::RL, R = LdsT::R, TE = LdsT::TE;
     constexpr int NL = RL * RL, NIT = (NL + THREADS - 1) / THREADS;  // loaded cells per thread
     constexpr int NE = TE * TE, NEIT = (NE + THREADS - 1) / THREADS;  // extended-block cells
     const uint32_t M = v.M, NC = M * M;
-    const int own_x = (M - I0 < (uint32_t)TILE) ? (int)(M - I0) : TILE;
-    const int own_y = (M - J0 < (uint32_t)TILE) ? (int)(M - J0) : TILE;
+    const int own_x = (M - I0 < (uint32_t)lim_x) ? (int)(M - I0) : lim_x;
+    const int own_y = (M - J0 < (uint32_t)lim_y) ? (int)(M - J0) : lim_y;
 
     const uint64_t sweep = v.dev->sweep + v.offset;
     const SweepDraws d = sweep_draws(v.seed_lo, v.seed_hi, sweep, v.W);
@@ -302,7 +373,8 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     // ---- load the region ----------------------------------------------------
     // Counts and slots 0 and 1 are loaded together (slot 1 is read whether
     // used or not: one dependent round trip fewer), slots 2 and 3 where the
-    // count asks for them.
+    // count asks for them (in the four-slot layout; the two-slot one only
+    // notes that they exist).
     if (tid == 0) L.big = 0u;
     // The waves issue their global loads at raised priority, so that they
     // leave before the arithmetic of the other workgroups on the CU
@@ -325,7 +397,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const uint32_t c = c_r[i], m = m_r[i];
-        if (m > 2) {
+        if (!kTwo && m > 2) {
             px_r[i].z = el(v.x_in, 2 * NC + c);
             py_r[i].z = el(v.y_in, 2 * NC + c);
             if (m > 3) {
@@ -349,13 +421,14 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         sy4.z = m > 2 ? sy4.z - cen : kFar;
         sx4.w = m > 3 ? sx4.w - cen : kFar;
         sy4.w = m > 3 ? sy4.w - cen : kFar;
-        L.x[li] = sx4;
-        L.y[li] = sy4;
+        rec_put(L, li, sx4, sy4);
         L.cnt[li] = (uint8_t)m;
         if (m > 2) L.big = 1u;
     }
     __syncthreads();
     stamp_at(stamp, tid, 1);
+    const bool big = __builtin_amdgcn_readfirstlane(L.big) != 0u;
+    if (kTwo && big) return false;
 
     // Tags of the extended block, loaded now and held in registers through
     // the passes: a disk keeps its slot while the passes move it.
@@ -371,8 +444,8 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             const uint32_t c = wrap_add(I0, ex, M) + __umul24(M, wrap_add(J0, ey, M));
             if (m > 0) tg_r[i].x = el(v.tag_in, c);
             if (m > 1) tg_r[i].y = el(v.tag_in, NC + c);
-            if (m > 2) tg_r[i].z = el(v.tag_in, 2 * NC + c);
-            if (m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
+            if (!kTwo && m > 2) tg_r[i].z = el(v.tag_in, 2 * NC + c);
+            if (!kTwo && m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -385,7 +458,7 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
     ctx.own_x = own_x;
     ctx.own_y = own_y;
     ctx.cen = cen;
-    ctx.big = __builtin_amdgcn_readfirstlane(L.big) != 0u;
+    ctx.big = big;
     // I0 and J0 are even, so the colour parity in region coordinates equals
     // the global one
     uint32_t col[4];
@@ -396,10 +469,10 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
         // each colour has its own instantiation with compile-time neighbour
         // offsets
         switch (col[p]) {
-        case 0: run_pass<TILE, THREADS, 0, 0>(L, v, ctx, tid, p, trials, accepts); break;
-        case 1: run_pass<TILE, THREADS, 1, 0>(L, v, ctx, tid, p, trials, accepts); break;
-        case 2: run_pass<TILE, THREADS, 0, 1>(L, v, ctx, tid, p, trials, accepts); break;
-        default: run_pass<TILE, THREADS, 1, 1>(L, v, ctx, tid, p, trials, accepts); break;
+        case 0: run_pass<LdsT, THREADS, 0, 0>(L, v, ctx, tid, p, trials, accepts); break;
+        case 1: run_pass<LdsT, THREADS, 1, 0>(L, v, ctx, tid, p, trials, accepts); break;
+        case 2: run_pass<LdsT, THREADS, 0, 1>(L, v, ctx, tid, p, trials, accepts); break;
+        default: run_pass<LdsT, THREADS, 1, 1>(L, v, ctx, tid, p, trials, accepts); break;
         }
         __syncthreads();
         stamp_at(stamp, tid, 2 + p);
@@ -423,7 +496,8 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             const bool in_ext = f < NE && ex <= own_x && ey <= own_y;
             const int li = pidx<R>(ex + kHalo, ey + kHalo);
             const uint32_t m = in_ext ? L.cnt[li] : 0u;
-            const float4 sx4 = L.x[in_ext ? li : 0], sy4 = L.y[in_ext ? li : 0];
+            float4 sx4, sy4;
+            rec_get(L, in_ext ? li : 0, sx4, sy4);
             float4 ux, uy;
             ux.x = sx4.x + cen;
             ux.y = sx4.y + cen;
@@ -512,39 +586,82 @@ __device__ __forceinline__ void fused_tile(Lds<TILE> &L, const View &v, int tid,
             }
         }
     };
-    if (ctx.big) rebin(std::integral_constant<int, 4>{});
+    if (!kTwo && ctx.big) rebin(std::integral_constant<int, 4>{});
     else rebin(std::integral_constant<int, 2>{});
     count_trials((DevScalars *)v.dev, trials, accepts);
     if (stamp) {
         __syncthreads();
         stamp_at(stamp, tid, 7);
     }
+    return true;
 }
 
-template <int TILE, int THREADS>
+// Bytes of dynamic LDS a tile shape needs: its own records, and in the
+// two-slot form also those of the four-slot sub-tiles it may fall back on.
+template <int TILE, bool TWO>
+constexpr size_t tile_lds_bytes() {
+    if constexpr (TWO)
+        return sizeof(Lds2<TILE>) > sizeof(Lds<sub_tile<TILE>()>) ? sizeof(Lds2<TILE>)
+                                                                  : sizeof(Lds<sub_tile<TILE>()>);
+    else
+        return sizeof(Lds<TILE>);
+}
+
+// One tile of side TILE at (I0, J0).  The two-slot form holds the region in
+// two-slot records; where the region holds a more crowded cell (rare: three
+// disks need a cell wider than 2 sigma and a corner-to-corner arrangement),
+// the same block runs as two by two four-slot sub-tiles, each with its own
+// halo, which gives the same trajectory.
+template <int TILE, int THREADS, bool TWO, typename View>
+__device__ __forceinline__ void tile_work(unsigned char *lds, const View &v, int tid, uint32_t I0,
+                                          uint32_t J0, unsigned long long *stamp) {
+    if constexpr (!TWO) {
+        fused_tile<Lds<TILE>, THREADS>(*reinterpret_cast<Lds<TILE> *>(lds), v, tid, I0, J0, TILE,
+                                       TILE, stamp);
+    } else {
+        if (fused_tile<Lds2<TILE>, THREADS>(*reinterpret_cast<Lds2<TILE> *>(lds), v, tid, I0, J0,
+                                            TILE, TILE, stamp))
+            return;
+        constexpr int SUB = sub_tile<TILE>();
+        Lds<SUB> &L4 = *reinterpret_cast<Lds<SUB> *>(lds);
+        for (int sj = 0; sj < TILE; sj += SUB)
+            for (int si = 0; si < TILE; si += SUB) {
+                __syncthreads();  // every read of the previous layout is done
+                if (I0 + (uint32_t)si < v.M && J0 + (uint32_t)sj < v.M)
+                    fused_tile<Lds<SUB>, THREADS>(L4, v, opaque_tid(), I0 + si, J0 + sj,
+                                                  TILE - si < SUB ? TILE - si : SUB,
+                                                  TILE - sj < SUB ? TILE - sj : SUB, nullptr);
+            }
+        if (stamp) {  // the sub-tiles' whole time is booked as the first colour pass
+            __syncthreads();
+            for (int k = 2; k < 8; ++k) stamp_at(stamp, tid, k);
+        }
+    }
+}
+
+template <int TILE, int THREADS, bool TWO>
 __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint32_t nty,
                                                    uint32_t per_xcd, unsigned long long *stamps) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
     // Consecutive workgroups go to different XCDs; give each XCD a
     // contiguous run of tiles so that shared halo cells meet in its L2.
     const uint32_t tile = (blockIdx.x % 8u) * per_xcd + blockIdx.x / 8u;
     if (tile >= ntx * nty) return;
     unsigned long long *stamp = stamps ? stamps + kStampWords * (size_t)tile : nullptr;
     stamp_at(stamp, (int)threadIdx.x, 8);
-    fused_tile<TILE, THREADS>(L, v, (int)threadIdx.x, (tile % ntx) * TILE, (tile / ntx) * TILE, stamp);
+    tile_work<TILE, THREADS, TWO>(lds_raw, v, (int)threadIdx.x, (tile % ntx) * TILE,
+                                  (tile / ntx) * TILE, stamp);
 }
 
 // Persistent form for a batch of independent boxes: workgroups stride over
 // a work list of (box, tile) items, item = box << 20 | tile.  All boxes of a
 // batch advance in step, so one buffer parity serves them all.
-template <int TILE, int THREADS>
+template <int TILE, int THREADS, bool TWO>
 __global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restrict__ views,
                                                          const uint32_t *__restrict__ items,
                                                          uint32_t n_items, uint32_t parity,
                                                          uint32_t offset) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    Lds<TILE> &L = *reinterpret_cast<Lds<TILE> *>(lds_raw);
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const uint32_t item = items[it], box = item >> 20, tile = item & 0xFFFFFu;
         const BoxView &src = views[2 * box + parity];
@@ -573,62 +690,69 @@ __global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restri
         v.seed_hi = src.seed_hi;
         v.offset = offset;
         const uint32_t ntx = (v.M + TILE - 1) / TILE;
-        fused_tile<TILE, THREADS>(L, v, opaque_tid(), (tile % ntx) * TILE, (tile / ntx) * TILE,
-                                  nullptr);
+        tile_work<TILE, THREADS, TWO>(lds_raw, v, opaque_tid(), (tile % ntx) * TILE,
+                                      (tile / ntx) * TILE, nullptr);
         __syncthreads();
     }
 }
 
 namespace {
-template <int TILE, int THREADS>
+template <int TILE, int THREADS, bool TWO>
 void launch_t(const BoxView &v, hipStream_t st, unsigned long long *stamps) {
     const uint32_t ntx = (v.M + TILE - 1) / TILE, nty = ntx;
     const uint32_t nt = ntx * nty, per_xcd = (nt + 7) / 8;
-    const size_t lds = sizeof(Lds<TILE>);
+    const size_t lds = tile_lds_bytes<TILE, TWO>();
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_fused<TILE, THREADS>,
+        (void)hipFuncSetAttribute((const void *)k_fused<TILE, THREADS, TWO>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    k_fused<TILE, THREADS><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd, stamps);
+    k_fused<TILE, THREADS, TWO><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd, stamps);
 }
 
-template <int TILE, int THREADS>
+template <int TILE, int THREADS, bool TWO>
 void launch_batch_t(const BoxView *views, const uint32_t *items, uint32_t n_items, uint32_t grid,
                     uint32_t parity, uint32_t offset, hipStream_t st) {
-    const size_t lds = sizeof(Lds<TILE>);
+    const size_t lds = tile_lds_bytes<TILE, TWO>();
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_fused_batch<TILE, THREADS>,
+        (void)hipFuncSetAttribute((const void *)k_fused_batch<TILE, THREADS, TWO>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    k_fused_batch<TILE, THREADS><<<grid, THREADS, lds, st>>>(views, items, n_items, parity, offset);
+    k_fused_batch<TILE, THREADS, TWO><<<grid, THREADS, lds, st>>>(views, items, n_items, parity,
+                                                                   offset);
 }
 
-template <int TILE, int THREADS>
+template <int TILE, int THREADS, bool TWO>
 int occupancy_t() {
     int blocks = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fused_batch<TILE, THREADS>, THREADS,
-                                                       sizeof(Lds<TILE>));
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fused_batch<TILE, THREADS, TWO>,
+                                                       THREADS, tile_lds_bytes<TILE, TWO>());
     return blocks;
 }
 
 struct Entry {
     uint32_t tile, threads;
+    bool two;  // two-slot records
     void (*fn)(const BoxView &, hipStream_t, unsigned long long *);
     void (*batch)(const BoxView *, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                   hipStream_t);
     int (*occ)();
 };
+#define MPMC_SHAPE(T, N, TWO) \
+    {T, N, TWO, launch_t<T, N, TWO>, launch_batch_t<T, N, TWO>, occupancy_t<T, N, TWO>}
+// The 34- and 48-cell tiles hold two-slot records: 35 KB of LDS and four
+// workgroups of 256 threads per CU, 62 KB and two of 512.  Their smaller
+// halo pays where a launch runs many rounds of workgroups.
 const Entry kShapes[] = {
-    {8, 64, launch_t<8, 64>, launch_batch_t<8, 64>, occupancy_t<8, 64>},       {8, 128, launch_t<8, 128>, launch_batch_t<8, 128>, occupancy_t<8, 128>},
-    {16, 128, launch_t<16, 128>, launch_batch_t<16, 128>, occupancy_t<16, 128>},   {16, 256, launch_t<16, 256>, launch_batch_t<16, 256>, occupancy_t<16, 256>},
-    {24, 256, launch_t<24, 256>, launch_batch_t<24, 256>, occupancy_t<24, 256>},   {32, 256, launch_t<32, 256>, launch_batch_t<32, 256>, occupancy_t<32, 256>},
-    {32, 512, launch_t<32, 512>, launch_batch_t<32, 512>, occupancy_t<32, 512>},   {48, 512, launch_t<48, 512>, launch_batch_t<48, 512>, occupancy_t<48, 512>},
-    {48, 1024, launch_t<48, 1024>, launch_batch_t<48, 1024>, occupancy_t<48, 1024>}, {56, 1024, launch_t<56, 1024>, launch_batch_t<56, 1024>, occupancy_t<56, 1024>},
+    MPMC_SHAPE(8, 64, false),    MPMC_SHAPE(8, 128, false),  MPMC_SHAPE(16, 128, false),
+    MPMC_SHAPE(16, 256, false),  MPMC_SHAPE(24, 256, false), MPMC_SHAPE(32, 256, false),
+    MPMC_SHAPE(32, 512, false),  MPMC_SHAPE(34, 256, true),  MPMC_SHAPE(48, 512, true),
+    MPMC_SHAPE(48, 1024, false), MPMC_SHAPE(56, 1024, false),
 };
+#undef MPMC_SHAPE
 }  // namespace
 
 const FusedShape *fused_shapes(uint32_t *count) {
@@ -637,6 +761,26 @@ const FusedShape *fused_shapes(uint32_t *count) {
         s[i] = FusedShape{kShapes[i].tile, kShapes[i].threads};
     *count = (uint32_t)(sizeof(kShapes) / sizeof(kShapes[0]));
     return s;
+}
+
+bool fused_tune_candidate(const FusedShape &s, uint64_t tiles) {
+    for (const Entry &e : kShapes)
+        if (e.tile == s.tile && e.threads == s.threads) {
+            if (!e.two) return true;
+            // A launch of few rounds ends in a tail where the last workgroup
+            // of a CU runs alone; the larger the tile, the longer that tail.
+            // At N = 1024^2 (one round of 34-cell tiles) it costs more than
+            // the smaller halo saves: 51 against 35 us per sweep; at
+            // N = 4096^2 (16 rounds) the 34-cell tile wins, 406 against
+            // 450 us.  The tuner also times shapes on the state it is given,
+            // often a lattice start, whose uniform tiles hide that tail.
+            int dev = 0, cus = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            const uint64_t per_cu = e.occ() > 0 ? (uint64_t)e.occ() : 1u;
+            return tiles >= 4u * per_cu * (uint64_t)(cus > 0 ? cus : 256);
+        }
+    return false;
 }
 
 bool fused_supported(const BoxView &v, const FusedShape &s) {

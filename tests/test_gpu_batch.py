@@ -43,7 +43,7 @@ def test_batch_schedules_agree(gpu_lib):
     ref = gpu_lib.Batch(N, eta, seed, step_m=40)
     ref.set_schedule(0, 1)  # per-box simple kernels
     ref.sweep(12)
-    for tile, threads in [(8, 128), (24, 256), (48, 512)]:
+    for tile, threads in [(8, 128), (24, 256), (34, 256), (48, 512)]:
         bt = gpu_lib.Batch(N, eta, seed, step_m=40)
         bt.set_schedule(tile, threads)
         bt.sweep(12)

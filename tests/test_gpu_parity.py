@@ -70,11 +70,13 @@ def test_shuffled_trials_bit_exact(gpu_lib, n_trial):
 SPARSE = dict(N=64 * 64, eta=0.35, seed=3, lattice=0, step_m=200)
 
 
-@pytest.mark.parametrize("tile,threads", [(8, 64), (24, 256)])
+@pytest.mark.parametrize("tile,threads", [(8, 64), (24, 256), (34, 256), (48, 512)])
 def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
     """Cells 2.8 sigma wide in a dilute box hold three disks now and then:
     the fused kernel tests slots 2 and 3 only in tiles that hold such a
-    cell, and both forms must give the oracle's trajectory."""
+    cell, and both forms must give the oracle's trajectory.  The 34- and
+    48-cell tiles keep two slots per cell in LDS and run a tile with such a
+    cell as four-slot sub-tiles instead."""
     g = gpu_box(gpu_lib, **SPARSE, cell_min=2.8, schedule="simple")
     g.set_schedule("fused", tile, threads)
     o = OracleBox(**SPARSE, cell_min=2.8)
@@ -108,7 +110,7 @@ def test_schedule_invariance_all_shapes(gpu_lib):
     ref.sweep(20)
     rc = ref.cells()
     shapes = [(8, 64), (8, 128), (16, 128), (16, 256), (24, 256), (32, 256), (32, 512),
-              (48, 512), (48, 1024)]
+              (34, 256), (48, 512), (48, 1024)]
     for tile, threads in shapes:
         b = gpu_box(gpu_lib, **TRI_65536, schedule="simple")
         b.set_schedule("fused", tile, threads)
