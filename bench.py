@@ -246,7 +246,8 @@ def phases_bench(args):
     clock stamps at the phase boundaries of every tile (mpmc_profile_phases),
     mean microseconds per tile."""
     import paper_1211_1645_amd.mpmc as mp
-    box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular")
+    box = mp.Box(N_DISKS, ETA, seed=args.seed, step_m=20, lattice="triangular",
+                 schedule="fused" if args.tile else "auto", tile=args.tile)
     step_m, _ = tune_step(box)
     box.sweep(200)
     info = box.info()
@@ -573,6 +574,7 @@ def scale_bench(args):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         box = mp.Box(SCALE_N, ETA, seed=args.seed, step_m=55, lattice="triangular",
+                     schedule="fused" if args.tile else "auto", tile=args.tile,
                      stream=stream.cuda_stream)
         box.set_graphs(args.sweeps)
         step_m, _ = tune_step(box, block=20)

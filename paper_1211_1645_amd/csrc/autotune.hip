@@ -154,7 +154,7 @@ static int autotune(Box *b, FusedShape *best) {
 }
 
 static uint32_t default_threads(uint32_t tile) {
-    return tile <= 8 ? 64 : tile <= 34 ? 256 : 1024;
+    return tile <= 8 ? 64 : tile <= 34 ? 256 : tile <= 48 ? 512 : 1024;
 }
 
 int Box::choose_schedule() {
