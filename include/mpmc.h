@@ -327,16 +327,22 @@ int mpmc_tau(const double *C, uint32_t maxlag, double lo, double hi, double *tau
              double *tau_int);
 
 /* Sweep schedule of an existing box: MPMC_SCHED_SIMPLE, MPMC_SCHED_FUSED
- * with the given tile side and threads per workgroup (0 = default), or
- * MPMC_SCHED_AUTO (autotune: time every fused shape that fits on this machine's
- * state, keep the fastest; cached per device, M and n_trial for the
+ * with the given tile side and threads per workgroup (0 = default: 64 for
+ * tile 8, 256 up to tile 34, 512 for 48, 1024 above), or MPMC_SCHED_AUTO
+ * (autotune: time every fused shape that fits on this machine's state, keep the
+ * fastest; cached per device, M and n_trial for the
  * process, and across processes in the text file named by the environment
  * variable MPMC_TUNE_CACHE if it is set: one line "<arch> <CUs> <M>
  * <n_trial> <tile> <threads>" per choice, read before tuning and appended
  * after; lines whose shape does not fit are ignored, and a file that cannot
  * be read or written only costs the tuning).  The state and the trajectory
- * are unaffected.  MPMC_EINVAL if the shape does not fit
- * (fused tiles need cells of at most 4 disks and an even tile <= M). */
+ * are unaffected.  Shapes (tile, threads): (8, 64), (8, 128), (16, 128),
+ * (16, 256), (24, 256), (32, 256), (32, 512), (34, 256), (48, 512),
+ * (48, 1024), (56, 1024); the 34- and 48-cell ones keep two slots per cell
+ * in LDS (a tile whose region holds a fuller cell runs as four-slot
+ * sub-tiles) and are autotuned only where a sweep runs at least four rounds
+ * of workgroups.  MPMC_EINVAL if the shape is not one of these or does not
+ * fit (fused tiles need cells of at most 4 slots and tile + 10 <= M). */
 int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t threads);
 
 /* Phase profile of the fused sweep kernel: runs `sweeps` sweeps (the chain
@@ -350,8 +356,9 @@ int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t thr
  * the sweeps: [9] the span from the first workgroup's entry to the last
  * one's end (us), [10] the mean number of tiles in flight over that span
  * (summed entry-to-end time / span), [11] the time from the first entry to
- * the last (us).  Allocates a stamp buffer for the call.  MPMC_EINVAL unless
- * the box runs the fused schedule. */
+ * the last (us).  A two-slot tile that runs as four-slot sub-tiles books
+ * their whole time under colour pass 1.  Allocates a stamp buffer for the
+ * call.  MPMC_EINVAL unless the box runs the fused schedule. */
 int mpmc_profile_phases(mpmc_box b, uint32_t sweeps, double *phase_us);
 
 /* Long runs replay a captured HIP graph of this many sweeps (even, default
