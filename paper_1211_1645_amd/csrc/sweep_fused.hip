@@ -71,7 +71,7 @@ struct Lds {
     float4 y[NC];
     uint8_t cnt[NC];
     uint16_t gcnt[TE * TE];  // re-bin: per old cell, disks per wrap class, 3 bits each
-    uint32_t big;            // some region cell holds more than two disks
+    uint32_t big[16];        // per wave: a cell it loaded holds more than two disks
 };
 
 // Two-slot records (x0, x1, y0, y1), half the LDS of the four-slot form, so
@@ -89,7 +89,7 @@ struct Lds2 {
     float4 xy[NC];
     uint8_t cnt[NC];
     uint16_t gcnt[TE * TE];
-    uint32_t big;
+    uint32_t big[16];
 };
 
 // Side of the four-slot sub-tiles that stand in for a two-slot tile of side
@@ -356,6 +356,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
                                            uint32_t J0, int lim_x, int lim_y,
                                            unsigned long long *stamp) {
     constexpr bool kTwo = LdsT::kTwo;
+    static_assert(THREADS % 64 == 0 && THREADS <= 64 * 16, "whole waves, at most 16");
     constexpr int RL = LdsT::RL, R = LdsT::R, TE = LdsT::TE;
     constexpr int NL = RL * RL, NIT = (NL + THREADS - 1) / THREADS;  // loaded cells per thread
     constexpr int NE = TE * TE, NEIT = (NE + THREADS - 1) / THREADS;  // extended-block cells
@@ -375,7 +376,6 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     // used or not: one dependent round trip fewer), slots 2 and 3 where the
     // count asks for them (in the four-slot layout; the two-slot one only
     // notes that they exist).
-    if (tid == 0) L.big = 0u;
     // The waves issue their global loads at raised priority, so that they
     // leave before the arithmetic of the other workgroups on the CU
     // (35.6 against 36.0 us per sweep in the benchmark's flow).
@@ -406,6 +406,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
             }
         }
     }
+    bool crowded = false;
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const int e = tid + i * THREADS;
@@ -423,11 +424,19 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
         sy4.w = m > 3 ? sy4.w - cen : kFar;
         rec_put(L, li, sx4, sy4);
         L.cnt[li] = (uint8_t)m;
-        if (m > 2) L.big = 1u;
+        crowded |= m > 2;
     }
+    // Every wave writes its own word, so no word needs clearing first: a
+    // shared flag cleared by one thread and set by others is not ordered
+    // without a barrier between the two.
+    const bool wave_crowded = __any((int)crowded);
+    if ((tid & 63) == 0) L.big[tid >> 6] = wave_crowded ? 1u : 0u;
     __syncthreads();
     stamp_at(stamp, tid, 1);
-    const bool big = __builtin_amdgcn_readfirstlane(L.big) != 0u;
+    uint32_t any_big = 0;
+#pragma unroll
+    for (int w = 0; w < THREADS / 64; ++w) any_big |= L.big[w];
+    const bool big = __builtin_amdgcn_readfirstlane(any_big) != 0u;
     if (kTwo && big) return false;
 
     // Tags of the extended block, loaded now and held in registers through

@@ -90,6 +90,24 @@ def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
     assert g.validate() == (0, 0)
 
 
+def test_two_slot_tiles_keep_every_disk_over_long_runs(gpu_lib):
+    """N = 1024^2 at eta = 0.716 holds a few cells of three disks in most
+    sweeps, so the 34-cell two-slot tile runs some tiles as four-slot
+    sub-tiles in most launches.  Over 6000 sweeps the state stays valid
+    (every tag once, offsets inside their cells, no overlap) and equals the
+    four-slot 24-cell tile's trajectory bit for bit."""
+    cfg = dict(N=1024 * 1024, eta=0.716, seed=4, lattice=1, step_m=55)
+    a = gpu_box(gpu_lib, **cfg, schedule="fused", tile=34)
+    b = gpu_box(gpu_lib, **cfg, schedule="fused", tile=24)
+    for _ in range(6):
+        a.sweep(1000)
+        b.sweep(1000)
+        assert a.validate() == (0, 0)
+    for x, y in zip(a.cells(), b.cells()):
+        assert np.array_equal(x, y)
+    assert a.info()["trials"] == b.info()["trials"]
+
+
 def test_n65536_triangular_trajectory_bit_exact(gpu_lib):
     g = gpu_box(gpu_lib, **TRI_65536)  # autotuned fused schedule
     assert g.info()["schedule"] == 2
