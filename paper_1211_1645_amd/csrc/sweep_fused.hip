@@ -75,9 +75,11 @@ struct Lds {
 };
 
 // Two-slot records (x0, x1, y0, y1), half the LDS of the four-slot form, so
-// that a larger tile still fits four workgroups per CU.  A region with a
-// cell of more than two disks cannot be held this way: the tile then runs
-// as four-slot sub-tiles instead.
+// that a larger tile still fits four workgroups per CU.  Slots 2 and 3 of
+// the few cells of more than two disks go to a side table of kSide
+// entries; a region with more such cells runs as four-slot sub-tiles.
+constexpr int kSide = 32;         // side-table entries of a two-slot region
+constexpr uint8_t kNoSide = 0xFF;  // a cell without a side entry
 template <int TILE_>
 struct Lds2 {
     static constexpr int TILE = TILE_;
@@ -87,9 +89,13 @@ struct Lds2 {
     static constexpr int NC = R * R;
     static constexpr int TE = TILE + 1;
     float4 xy[NC];
+    float4 side[kSide];         // crowded cells' slots 2 and 3: x2, x3, y2, y3
     uint8_t cnt[NC];
+    uint8_t sidx[NC];           // crowded regions only: the cell's side entry or kNoSide
     uint16_t gcnt[TE * TE];
+    uint16_t side_at[kSide];    // region coordinates of a side entry's cell, x | y << 8
     uint32_t big[16];
+    uint32_t nside;
 };
 
 // Side of the four-slot sub-tiles that stand in for a two-slot tile of side
@@ -165,6 +171,38 @@ template <int T>
 __device__ __forceinline__ void rec_put(Lds2<T> &L, int e, const float4 &mx, const float4 &my) {
     L.xy[e] = make_float4(mx.x, mx.y, my.x, my.y);
 }
+// The records of a two-slot region cell with its slots 2 and 3 from the
+// side table (crowded regions only), and their write-back.
+template <int T>
+__device__ __forceinline__ void rec_get_side(const Lds2<T> &L, int e, float4 &mx, float4 &my) {
+    rec_get(L, e, mx, my);
+    const uint32_t k = L.sidx[e];
+    if (k != kNoSide) {
+        const float4 r = L.side[k];
+        mx.z = r.x;
+        mx.w = r.y;
+        my.z = r.z;
+        my.w = r.w;
+    }
+}
+template <int T>
+__device__ __forceinline__ void rec_put_side(Lds2<T> &L, int e, const float4 &mx,
+                                             const float4 &my) {
+    rec_put(L, e, mx, my);
+    const uint32_t k = L.sidx[e];
+    if (k != kNoSide) L.side[k] = make_float4(mx.z, mx.w, my.z, my.w);
+}
+// The records of a cell with SL slots: in the two-slot layout slots 2 and 3
+// come from the side table.
+template <int SL, int T>
+__device__ __forceinline__ void rec_get_slots(const Lds<T> &L, int e, float4 &mx, float4 &my) {
+    rec_get(L, e, mx, my);
+}
+template <int SL, int T>
+__device__ __forceinline__ void rec_get_slots(const Lds2<T> &L, int e, float4 &mx, float4 &my) {
+    if constexpr (SL > 2) rec_get_side(L, e, mx, my);
+    else rec_get(L, e, mx, my);
+}
 // Slots 0 and 1 of a neighbour cell.
 template <int T>
 __device__ __forceinline__ void rec_get2(const Lds<T> &L, int e, float2 &qx, float2 &qy) {
@@ -185,6 +223,7 @@ struct PassCtx {
     int own_x, own_y;
     float cen;
     bool big;
+    int nside;  // side-table entries in use (two-slot layout, crowded region)
 };
 
 // Does a disk at centred offsets (xn, yn) of region cell (CX + 2 ax, CY + 2 ay)
@@ -195,8 +234,11 @@ struct PassCtx {
 // separations of a row of three cells (each rounded as in overlap_f32) are
 // reduced by a running minimum and compared once per row: the minimum is
 // below 4 exactly when one of them is.  The rare four-slot form compares the
-// neighbours' pairs one by one, which holds fewer registers live.
-template <int SL, int H, int CX, int CY, typename LdsT>
+// neighbours' pairs one by one, which holds fewer registers live.  NB is the
+// number of neighbour slots read from the records (the two-slot layout's
+// crowded form tests all four own slots but reads two per neighbour and
+// takes the neighbours' slots 2 and 3 from the side table).
+template <int SL, int H, int CX, int CY, int NB = SL, typename LdsT>
 __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_t slot,
                                              const float4 &mx, const float4 &my, float xn,
                                              float yn, float w) {
@@ -223,7 +265,7 @@ __device__ __forceinline__ bool overlaps_any(const LdsT &L, int base_ax, uint32_
             const int cxn = (CX + di) & 1, cyn = (CY + dj) & 1;
             const int offx = (CX + di + 2) / 2 - 1, offy = (CY + dj + 2) / 2 - 1;
             const int ne = (cxn | (cyn << 1)) * H * H + base_ax + offx + H * offy;
-            if constexpr (SL > 2) {
+            if constexpr (NB > 2) {
                 const float4 qx = L.x[ne], qy = L.y[ne];
                 bad |= overlap_f32(qx.x - gx, qy.x - gy);
                 bad |= overlap_f32(qx.y - gx, qy.y - gy);
@@ -273,6 +315,45 @@ __device__ __forceinline__ bool try_move(const LdsT &L, int base_ax, uint32_t sl
     return acc;
 }
 
+// Does a disk at centred offsets (xn, yn) of region cell (rx, ry) overlap
+// slot 2 or 3 of a neighbouring crowded cell?  Those are the side table's
+// entries whose cell is one of the eight neighbours (the own cell's entry is
+// tested with its records); the separations are formed as in overlaps_any.
+template <typename LdsT>
+__device__ __forceinline__ bool side_overlaps(const LdsT &L, int nside, int rx, int ry, float xn,
+                                              float yn, float w) {
+    bool bad = false;
+    for (int k = 0; k < nside; ++k) {
+        const uint32_t at = L.side_at[k];
+        const int di = (int)(at & 0xFFu) - rx, dj = (int)(at >> 8) - ry;
+        if (di < -1 || di > 1 || dj < -1 || dj > 1 || (di == 0 && dj == 0)) continue;
+        const float gx = di == 0 ? xn : (di > 0 ? xn - w : xn + w);
+        const float gy = dj == 0 ? yn : (dj > 0 ? yn - w : yn + w);
+        const float4 r = L.side[k];
+        bad |= overlap_f32(r.x - gx, r.z - gy);
+        bad |= overlap_f32(r.y - gx, r.w - gy);
+    }
+    return bad;
+}
+
+// try_move for a crowded two-slot region: any of the own cell's four slots
+// (slots 2 and 3 loaded from the side table into mx, my), the neighbours'
+// slots 0 and 1 from their records and slots 2 and 3 from the side table.
+template <int H, int CX, int CY, typename LdsT>
+__device__ __forceinline__ bool try_move_side(const LdsT &L, int base_ax, int rx, int ry,
+                                              int nside, uint32_t slot, float4 &mx, float4 &my,
+                                              float dxs, float dys, float lo_b, float hi_b,
+                                              float w) {
+    const float xn = pick4(mx, slot) + dxs, yn = pick4(my, slot) + dys;
+    const bool inside = xn >= lo_b && xn < hi_b && yn >= lo_b && yn < hi_b;
+    const bool acc = inside &&
+                     !overlaps_any<4, H, CX, CY, 2>(L, base_ax, slot, mx, my, xn, yn, w) &&
+                     !side_overlaps(L, nside, rx, ry, xn, yn, w);
+    mx = acc ? put4(mx, slot, xn) : mx;
+    my = acc ? put4(my, slot, yn) : my;
+    return acc;
+}
+
 // One colour sub-sweep over the LDS region: pass p updates the cells of
 // colour (CX, CY) with region coordinates in [p + 1, RL - p - 1), one lane per
 // cell of that rectangle of the colour plane; lanes of empty cells idle.
@@ -315,7 +396,12 @@ __device__ __forceinline__ void run_pass(LdsT &L, const View &v, const PassCtx &
         }
         const int base_ax = a;  // ax + H * ay inside a plane
         float4 mx, my;
-        rec_get(L, e, mx, my);
+        if constexpr (LdsT::kTwo) {
+            if (ctx.big) rec_get_side(L, e, mx, my);
+            else rec_get(L, e, mx, my);
+        } else {
+            rec_get(L, e, mx, my);
+        }
         for (uint32_t t = 0; t < v.n_trial; ++t) {
             const Words w4 = draw(v.seed_lo, v.seed_hi, ctx.sweep, cell, t, kStreamTrial);
             const uint32_t slot = (v.n_trial == 1) ? mulhi32(w4.w0, n)
@@ -325,14 +411,22 @@ __device__ __forceinline__ void run_pass(LdsT &L, const View &v, const PassCtx &
             if (own) ++trials;
             bool acc;
             if constexpr (LdsT::kTwo)
-                acc = try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
+                acc = ctx.big ? try_move_side<H, CX, CY>(L, base_ax, rx, ry, ctx.nside, slot, mx, my,
+                                                         dxs, dys, lo_b, hi_b, w)
+                              : try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b,
+                                                       hi_b, w);
             else
                 acc = ctx.big
                           ? try_move<4, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w)
                           : try_move<2, H, CX, CY>(L, base_ax, slot, mx, my, dxs, dys, lo_b, hi_b, w);
             if (own && acc) ++accepts;
         }
-        rec_put(L, e, mx, my);
+        if constexpr (LdsT::kTwo) {
+            if (ctx.big) rec_put_side(L, e, mx, my);
+            else rec_put(L, e, mx, my);
+        } else {
+            rec_put(L, e, mx, my);
+        }
     }
 }
 
@@ -348,9 +442,9 @@ __device__ __forceinline__ void stamp_at(unsigned long long *stamp, int tid, int
 // The work of one tile: load, four colour passes, canonical write-back,
 // re-bin into the next sweep's grid, counts.  The tile owns the cells
 // [I0, I0 + lim_x) x [J0, J0 + lim_y) (lim <= TILE) that lie in the box.
-// In the two-slot layout a region holding a cell of more than two disks
-// makes it return false before it writes anything outside LDS; otherwise
-// it returns true.
+// In the two-slot layout a region holding more than kSide cells of more than
+// two disks makes it return false before it writes anything outside LDS;
+// otherwise it returns true.
 template <typename LdsT, int THREADS, typename View>
 __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint32_t I0,
                                            uint32_t J0, int lim_x, int lim_y,
@@ -437,7 +531,41 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
 #pragma unroll
     for (int w = 0; w < THREADS / 64; ++w) any_big |= L.big[w];
     const bool big = __builtin_amdgcn_readfirstlane(any_big) != 0u;
-    if (kTwo && big) return false;
+    int nside = 0;
+    if constexpr (kTwo) {
+        if (big) {
+            // The first wave lists the crowded cells in region order and
+            // loads their slots 2 and 3 into the side table.
+            if (tid < 64) {
+                uint32_t base = 0;
+                for (int e0 = 0; e0 < NL; e0 += 64) {
+                    const int e = e0 + tid;
+                    const int li = e < NL ? pidx<R>(e % RL, e / RL) : 0;
+                    const uint32_t m = e < NL ? (uint32_t)L.cnt[li] : 0u;
+                    const unsigned long long bal = __ballot(m > 2);
+                    const uint32_t idx =
+                        base + (uint32_t)__popcll(bal & ((1ull << (uint32_t)tid) - 1ull));
+                    const bool listed = m > 2 && idx < (uint32_t)kSide;
+                    if (e < NL) L.sidx[li] = listed ? (uint8_t)idx : kNoSide;
+                    if (listed) {
+                        const uint32_t c =
+                            wrap_add(gx0, e % RL, M) + __umul24(M, wrap_add(gy0, e / RL, M));
+                        const float x2 = el(v.x_in, 2 * NC + c) - cen;
+                        const float y2 = el(v.y_in, 2 * NC + c) - cen;
+                        const float x3 = m > 3 ? el(v.x_in, 3 * NC + c) - cen : kFar;
+                        const float y3 = m > 3 ? el(v.y_in, 3 * NC + c) - cen : kFar;
+                        L.side[idx] = make_float4(x2, x3, y2, y3);
+                        L.side_at[idx] = (uint16_t)((e % RL) | ((e / RL) << 8));
+                    }
+                    base += (uint32_t)__popcll(bal);
+                }
+                if (tid == 0) L.nside = base;
+            }
+            __syncthreads();
+            nside = (int)__builtin_amdgcn_readfirstlane(L.nside);
+            if (nside > kSide) return false;  // too many: four-slot sub-tiles
+        }
+    }
 
     // Tags of the extended block, loaded now and held in registers through
     // the passes: a disk keeps its slot while the passes move it.
@@ -453,8 +581,8 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
             const uint32_t c = wrap_add(I0, ex, M) + __umul24(M, wrap_add(J0, ey, M));
             if (m > 0) tg_r[i].x = el(v.tag_in, c);
             if (m > 1) tg_r[i].y = el(v.tag_in, NC + c);
-            if (!kTwo && m > 2) tg_r[i].z = el(v.tag_in, 2 * NC + c);
-            if (!kTwo && m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
+            if ((!kTwo || big) && m > 2) tg_r[i].z = el(v.tag_in, 2 * NC + c);
+            if ((!kTwo || big) && m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -468,6 +596,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     ctx.own_y = own_y;
     ctx.cen = cen;
     ctx.big = big;
+    ctx.nside = nside;
     // I0 and J0 are even, so the colour parity in region coordinates equals
     // the global one
     uint32_t col[4];
@@ -506,7 +635,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
             const int li = pidx<R>(ex + kHalo, ey + kHalo);
             const uint32_t m = in_ext ? L.cnt[li] : 0u;
             float4 sx4, sy4;
-            rec_get(L, in_ext ? li : 0, sx4, sy4);
+            rec_get_slots<SL>(L, in_ext ? li : 0, sx4, sy4);
             float4 ux, uy;
             ux.x = sx4.x + cen;
             ux.y = sx4.y + cen;
@@ -595,7 +724,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
             }
         }
     };
-    if (!kTwo && ctx.big) rebin(std::integral_constant<int, 4>{});
+    if (ctx.big) rebin(std::integral_constant<int, 4>{});
     else rebin(std::integral_constant<int, 2>{});
     count_trials((DevScalars *)v.dev, trials, accepts);
     if (stamp) {
@@ -617,10 +746,11 @@ constexpr size_t tile_lds_bytes() {
 }
 
 // One tile of side TILE at (I0, J0).  The two-slot form holds the region in
-// two-slot records; where the region holds a more crowded cell (rare: three
-// disks need a cell wider than 2 sigma and a corner-to-corner arrangement),
-// the same block runs as two by two four-slot sub-tiles, each with its own
-// halo, which gives the same trajectory.
+// two-slot records and the slots 2 and 3 of its crowded cells in a side
+// table; where the region holds more crowded cells than the table has
+// entries (a dilute box of wide cells), the same block runs as two by two
+// four-slot sub-tiles, each with its own halo, which gives the same
+// trajectory.
 template <int TILE, int THREADS, bool TWO, typename View>
 __device__ __forceinline__ void tile_work(unsigned char *lds, const View &v, int tid, uint32_t I0,
                                           uint32_t J0, unsigned long long *stamp) {
