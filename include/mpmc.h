@@ -339,10 +339,10 @@ int mpmc_tau(const double *C, uint32_t maxlag, double lo, double hi, double *tau
  * are unaffected.  Shapes (tile, threads): (8, 64), (8, 128), (16, 128),
  * (16, 256), (24, 256), (32, 256), (32, 512), (34, 256), (48, 512),
  * (48, 1024), (56, 1024); the 34- and 48-cell ones keep two slots per cell
- * in LDS (a tile whose region holds a fuller cell runs as four-slot
- * sub-tiles) and are autotuned only where a sweep runs at least four rounds
- * of workgroups.  MPMC_EINVAL if the shape is not one of these or does not
- * fit (fused tiles need cells of at most 4 slots and tile + 10 <= M). */
+ * in LDS and slots 2 and 3 of fuller cells in a side table of 32 entries (a
+ * region with more such cells runs as four-slot sub-tiles).  MPMC_EINVAL if
+ * the shape is not one of these or does not fit (fused tiles need cells of
+ * at most 4 slots and tile + 10 <= M). */
 int mpmc_set_schedule(mpmc_box b, uint32_t schedule, uint32_t tile, uint32_t threads);
 
 /* Phase profile of the fused sweep kernel: runs `sweeps` sweeps (the chain

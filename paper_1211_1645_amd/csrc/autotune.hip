@@ -131,8 +131,6 @@ static int autotune(Box *b, FusedShape *best) {
     for (int round = 0; round < 3; ++round)
         for (uint32_t i = 0; i < n; ++i) {
             if (!fused_supported(v, shapes[i])) continue;
-            const uint64_t nt = (b->g.M + shapes[i].tile - 1) / shapes[i].tile;
-            if (!fused_tune_candidate(shapes[i], nt * nt)) continue;
             float ms;
             rc = time_shape(b, shapes[i], 10, &ms);
             if (rc) return rc;

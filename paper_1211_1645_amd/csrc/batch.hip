@@ -204,12 +204,6 @@ struct Batch {
         FusedShape bs{0, 0};
         for (uint32_t i = 0; i < n; ++i) {
             if (!fits(shapes[i])) continue;
-            uint64_t tiles = 0;
-            for (Box *bx : boxes) {
-                const uint64_t nt = (bx->g.M + shapes[i].tile - 1) / shapes[i].tile;
-                tiles += nt * nt;
-            }
-            if (!fused_tune_candidate(shapes[i], tiles)) continue;
             float ms;
             rc = time_shape(shapes[i], &ms);
             if (rc) return rc;

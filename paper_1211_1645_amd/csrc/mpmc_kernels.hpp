@@ -43,9 +43,6 @@ void launch_advance(DevScalars *dev, uint32_t seed_lo, uint32_t seed_hi, uint32_
 // sweep_fused.hip
 struct FusedShape { uint32_t tile, threads; };
 bool fused_supported(const BoxView &v, const FusedShape &s);
-// Whether the autotuner times shape s for a launch of `tiles` workgroup
-// tiles (two-slot shapes only where the launch runs at least four rounds).
-bool fused_tune_candidate(const FusedShape &s, uint64_t tiles);
 const FusedShape *fused_shapes(uint32_t *count);
 // stamps (NULL normally): kStampWords realtime-clock words per tile, for
 // the phase profile

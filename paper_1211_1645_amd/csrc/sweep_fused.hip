@@ -444,10 +444,11 @@ __device__ __forceinline__ void stamp_at(unsigned long long *stamp, int tid, int
 // [I0, I0 + lim_x) x [J0, J0 + lim_y) (lim <= TILE) that lie in the box.
 // In the two-slot layout a region holding more than kSide cells of more than
 // two disks makes it return false before it writes anything outside LDS;
-// otherwise it returns true.
+// otherwise it returns true.  `pace` (uniform) selects the wave priorities
+// described at the region load.
 template <typename LdsT, int THREADS, typename View>
 __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint32_t I0,
-                                           uint32_t J0, int lim_x, int lim_y,
+                                           uint32_t J0, int lim_x, int lim_y, bool pace,
                                            unsigned long long *stamp) {
     constexpr bool kTwo = LdsT::kTwo;
     static_assert(THREADS % 64 == 0 && THREADS <= 64 * 16, "whole waves, at most 16");
@@ -470,9 +471,17 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     // used or not: one dependent round trip fewer), slots 2 and 3 where the
     // count asks for them (in the four-slot layout; the two-slot one only
     // notes that they exist).
-    // The waves issue their global loads at raised priority, so that they
-    // leave before the arithmetic of the other workgroups on the CU
-    // (35.6 against 36.0 us per sweep in the benchmark's flow).
+    // Wave priorities.  The global loads of the region and the tags are
+    // issued at raised priority, so that they leave before the arithmetic
+    // of the other workgroups on the CU.  In a launch of at most two rounds
+    // of workgroups (`pace`) the priority also falls as the tile progresses:
+    // 3 from here through the first colour pass, 2 in the second, 1 in the
+    // third and fourth, 0 in the re-bin.  The least advanced of the
+    // workgroups sharing a CU then issues first, so they keep pace and the
+    // last tiles of the launch do not run alone at one wave per SIMD.  At
+    // N = 1024^2, eta = 0.716 the one-round 34-cell tile sweeps in 31.2 us
+    // with it against 33.5 us without; at N = 4096^2 (16 rounds) it costs
+    // 6 %, and the other waves stay at 0 there.
     __builtin_amdgcn_s_setprio(3);
     uint32_t m_r[NIT], c_r[NIT];
     float4 px_r[NIT], py_r[NIT];
@@ -487,7 +496,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
         px_r[i] = make_float4(el(v.x_in, c), el(v.x_in, NC + c), kFar, kFar);
         py_r[i] = make_float4(el(v.y_in, c), el(v.y_in, NC + c), kFar, kFar);
     }
-    __builtin_amdgcn_s_setprio(0);
+    if (!pace) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int i = 0; i < NIT; ++i) {
         const uint32_t c = c_r[i], m = m_r[i];
@@ -570,7 +579,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     // Tags of the extended block, loaded now and held in registers through
     // the passes: a disk keeps its slot while the passes move it.
     uint4 tg_r[NEIT];
-    __builtin_amdgcn_s_setprio(3);
+    if (!pace) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int i = 0; i < NEIT; ++i) {
         const int f = tid + i * THREADS;
@@ -585,7 +594,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
             if ((!kTwo || big) && m > 3) tg_r[i].w = el(v.tag_in, 3 * NC + c);
         }
     }
-    __builtin_amdgcn_s_setprio(0);
+    if (!pace) __builtin_amdgcn_s_setprio(0);
 
     // ---- four colour sub-sweeps --------------------------------------------
     PassCtx ctx;
@@ -604,6 +613,13 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     for (int p = 0; p < 4; ++p) col[p] = colour_of_pass(d.perm, p);
     uint32_t trials = 0, accepts = 0;
     for (int p = 0; p < 4; ++p) {
+        if (pace) {
+            switch (p) {  // s_setprio takes an immediate
+            case 0: break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            default: __builtin_amdgcn_s_setprio(1); break;
+            }
+        }
         // each colour has its own instantiation with compile-time neighbour
         // offsets
         switch (col[p]) {
@@ -619,6 +635,7 @@ __device__ __forceinline__ bool fused_tile(LdsT &L, const View &v, int tid, uint
     // ---- canonical state of the own block; wrap classes for the next grid ---
     // Old cell (ex, ey) of the extended block sends its disks to new cell
     // (ex - wx, ey - wy) of the next sweep's grid, shifted by s'.
+    __builtin_amdgcn_s_setprio(0);
     const SweepDraws dn = sweep_draws(v.seed_lo, v.seed_hi, sweep + 1, v.W);
     const float sxn = (float)dn.kx * kQ, syn = (float)dn.ky * kQ;
     // Only the slots in use are read: two when no region cell holds more
@@ -753,13 +770,13 @@ constexpr size_t tile_lds_bytes() {
 // trajectory.
 template <int TILE, int THREADS, bool TWO, typename View>
 __device__ __forceinline__ void tile_work(unsigned char *lds, const View &v, int tid, uint32_t I0,
-                                          uint32_t J0, unsigned long long *stamp) {
+                                          uint32_t J0, bool pace, unsigned long long *stamp) {
     if constexpr (!TWO) {
         fused_tile<Lds<TILE>, THREADS>(*reinterpret_cast<Lds<TILE> *>(lds), v, tid, I0, J0, TILE,
-                                       TILE, stamp);
+                                       TILE, pace, stamp);
     } else {
         if (fused_tile<Lds2<TILE>, THREADS>(*reinterpret_cast<Lds2<TILE> *>(lds), v, tid, I0, J0,
-                                            TILE, TILE, stamp))
+                                            TILE, TILE, pace, stamp))
             return;
         constexpr int SUB = sub_tile<TILE>();
         Lds<SUB> &L4 = *reinterpret_cast<Lds<SUB> *>(lds);
@@ -769,7 +786,8 @@ __device__ __forceinline__ void tile_work(unsigned char *lds, const View &v, int
                 if (I0 + (uint32_t)si < v.M && J0 + (uint32_t)sj < v.M)
                     fused_tile<Lds<SUB>, THREADS>(L4, v, opaque_tid(), I0 + si, J0 + sj,
                                                   TILE - si < SUB ? TILE - si : SUB,
-                                                  TILE - sj < SUB ? TILE - sj : SUB, nullptr);
+                                                  TILE - sj < SUB ? TILE - sj : SUB, pace,
+                                                  nullptr);
             }
         if (stamp) {  // the sub-tiles' whole time is booked as the first colour pass
             __syncthreads();
@@ -780,7 +798,8 @@ __device__ __forceinline__ void tile_work(unsigned char *lds, const View &v, int
 
 template <int TILE, int THREADS, bool TWO>
 __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint32_t nty,
-                                                   uint32_t per_xcd, unsigned long long *stamps) {
+                                                   uint32_t per_xcd, uint32_t pace,
+                                                   unsigned long long *stamps) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     // Consecutive workgroups go to different XCDs; give each XCD a
     // contiguous run of tiles so that shared halo cells meet in its L2.
@@ -789,7 +808,7 @@ __global__ void __launch_bounds__(THREADS) k_fused(BoxView v, uint32_t ntx, uint
     unsigned long long *stamp = stamps ? stamps + kStampWords * (size_t)tile : nullptr;
     stamp_at(stamp, (int)threadIdx.x, 8);
     tile_work<TILE, THREADS, TWO>(lds_raw, v, (int)threadIdx.x, (tile % ntx) * TILE,
-                                  (tile / ntx) * TILE, stamp);
+                                  (tile / ntx) * TILE, pace != 0u, stamp);
 }
 
 // Persistent form for a batch of independent boxes: workgroups stride over
@@ -799,7 +818,7 @@ template <int TILE, int THREADS, bool TWO>
 __global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restrict__ views,
                                                          const uint32_t *__restrict__ items,
                                                          uint32_t n_items, uint32_t parity,
-                                                         uint32_t offset) {
+                                                         uint32_t offset, uint32_t pace) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const uint32_t item = items[it], box = item >> 20, tile = item & 0xFFFFFu;
@@ -830,12 +849,28 @@ __global__ void __launch_bounds__(THREADS) k_fused_batch(const BoxView *__restri
         v.offset = offset;
         const uint32_t ntx = (v.M + TILE - 1) / TILE;
         tile_work<TILE, THREADS, TWO>(lds_raw, v, opaque_tid(), (tile % ntx) * TILE,
-                                      (tile / ntx) * TILE, nullptr);
+                                      (tile / ntx) * TILE, pace != 0u, nullptr);
         __syncthreads();
     }
 }
 
 namespace {
+// Workgroups of a shape resident on the whole device at once (occupancy
+// per CU times CUs), taken once per shape.
+template <int TILE, int THREADS, bool TWO>
+uint32_t resident_t() {
+    static uint32_t slots = 0;
+    if (!slots) {
+        int blocks = 0, dev = 0, cus = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fused<TILE, THREADS, TWO>,
+                                                           THREADS, tile_lds_bytes<TILE, TWO>());
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        slots = (uint32_t)(blocks > 0 ? blocks : 1) * (uint32_t)(cus > 0 ? cus : 256);
+    }
+    return slots;
+}
+
 template <int TILE, int THREADS, bool TWO>
 void launch_t(const BoxView &v, hipStream_t st, unsigned long long *stamps) {
     const uint32_t ntx = (v.M + TILE - 1) / TILE, nty = ntx;
@@ -847,7 +882,9 @@ void launch_t(const BoxView &v, hipStream_t st, unsigned long long *stamps) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
-    k_fused<TILE, THREADS, TWO><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd, stamps);
+    const uint32_t pace = nt <= 2u * resident_t<TILE, THREADS, TWO>() ? 1u : 0u;
+    k_fused<TILE, THREADS, TWO><<<8 * per_xcd, THREADS, lds, st>>>(v, ntx, nty, per_xcd, pace,
+                                                                    stamps);
 }
 
 template <int TILE, int THREADS, bool TWO>
@@ -860,8 +897,9 @@ void launch_batch_t(const BoxView *views, const uint32_t *items, uint32_t n_item
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr = true;
     }
+    const uint32_t pace = n_items <= 2u * grid ? 1u : 0u;  // grid: every resident slot
     k_fused_batch<TILE, THREADS, TWO><<<grid, THREADS, lds, st>>>(views, items, n_items, parity,
-                                                                   offset);
+                                                                   offset, pace);
 }
 
 template <int TILE, int THREADS, bool TWO>
@@ -882,9 +920,9 @@ struct Entry {
 };
 #define MPMC_SHAPE(T, N, TWO) \
     {T, N, TWO, launch_t<T, N, TWO>, launch_batch_t<T, N, TWO>, occupancy_t<T, N, TWO>}
-// The 34- and 48-cell tiles hold two-slot records: 35 KB of LDS and four
-// workgroups of 256 threads per CU, 62 KB and two of 512.  Their smaller
-// halo pays where a launch runs many rounds of workgroups.
+// The 34- and 48-cell tiles hold two-slot records: 37 KB of LDS and four
+// workgroups of 256 threads per CU, 64 KB and two of 512.  At N = 1024^2,
+// eta = 0.716 (M = 1072) the 34-cell tile gives 1024 tiles, one round.
 const Entry kShapes[] = {
     MPMC_SHAPE(8, 64, false),    MPMC_SHAPE(8, 128, false),  MPMC_SHAPE(16, 128, false),
     MPMC_SHAPE(16, 256, false),  MPMC_SHAPE(24, 256, false), MPMC_SHAPE(32, 256, false),
@@ -900,26 +938,6 @@ const FusedShape *fused_shapes(uint32_t *count) {
         s[i] = FusedShape{kShapes[i].tile, kShapes[i].threads};
     *count = (uint32_t)(sizeof(kShapes) / sizeof(kShapes[0]));
     return s;
-}
-
-bool fused_tune_candidate(const FusedShape &s, uint64_t tiles) {
-    for (const Entry &e : kShapes)
-        if (e.tile == s.tile && e.threads == s.threads) {
-            if (!e.two) return true;
-            // A launch of few rounds ends in a tail where the last workgroup
-            // of a CU runs alone; the larger the tile, the longer that tail.
-            // At N = 1024^2 (one round of 34-cell tiles) it costs more than
-            // the smaller halo saves: 51 against 35 us per sweep; at
-            // N = 4096^2 (16 rounds) the 34-cell tile wins, 406 against
-            // 450 us.  The tuner also times shapes on the state it is given,
-            // often a lattice start, whose uniform tiles hide that tail.
-            int dev = 0, cus = 0;
-            (void)hipGetDevice(&dev);
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            const uint64_t per_cu = e.occ() > 0 ? (uint64_t)e.occ() : 1u;
-            return tiles >= 4u * per_cu * (uint64_t)(cus > 0 ? cus : 256);
-        }
-    return false;
 }
 
 bool fused_supported(const BoxView &v, const FusedShape &s) {
