@@ -75,8 +75,8 @@ def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
     """Cells 2.8 sigma wide in a dilute box hold three disks now and then:
     the fused kernel tests slots 2 and 3 only in tiles that hold such a
     cell, and both forms must give the oracle's trajectory.  The 34- and
-    48-cell tiles keep two slots per cell in LDS and run a tile with such a
-    cell as four-slot sub-tiles instead."""
+    48-cell tiles keep two slots per cell in LDS and slots 2 and 3 of such
+    cells (11 to 21 of them per region here) in their side table."""
     g = gpu_box(gpu_lib, **SPARSE, cell_min=2.8, schedule="simple")
     g.set_schedule("fused", tile, threads)
     o = OracleBox(**SPARSE, cell_min=2.8)
@@ -87,6 +87,40 @@ def test_fused_crowded_cells_bit_exact(gpu_lib, tile, threads):
         done = k
         assert_same_state(g, o)
     assert (g.cells()[0] >= 3).sum() > 0
+    assert g.validate() == (0, 0)
+
+
+CROWDED = dict(N=72 * 72, eta=0.50, seed=5, lattice=0, step_m=200)
+
+
+def crowded_per_region(cnt, side):
+    """Cells of three or more disks in every side x side window of the
+    periodic M x M grid (min, max over the windows)."""
+    c = (cnt >= 3).astype(np.int64)
+    M = c.shape[0]
+    cc = np.pad(c, ((0, side), (0, side)), mode="wrap")
+    S = np.pad(cc.cumsum(0).cumsum(1), ((1, 0), (1, 0)))
+    v = S[side:M + side, side:M + side] - S[:M, side:M + side] - S[side:M + side, :M] + S[:M, :M]
+    return int(v.min()), int(v.max())
+
+
+@pytest.mark.parametrize("tile,threads", [(34, 256), (48, 512)])
+def test_two_slot_tiles_with_more_crowded_cells_than_the_side_table(gpu_lib, tile, threads):
+    """Cells 2.82 sigma wide at eta = 0.5 (M = 64): every tile region holds
+    more than 32 cells of three or four disks, so every two-slot tile runs as
+    four-slot sub-tiles; the trajectory is the oracle's."""
+    g = gpu_box(gpu_lib, **CROWDED, cell_min=2.8, schedule="simple")
+    g.set_schedule("fused", tile, threads)
+    o = OracleBox(**CROWDED, cell_min=2.8)
+    M = g.info()["M"]
+    assert M == 64 and g.info()["w"] < 2.0 * math.sqrt(2.0)  # at most four disks a cell
+    done = 0
+    for k in (10, 100):
+        g.sweep(k - done)
+        o.sweep(k - done)
+        done = k
+        assert_same_state(g, o)
+        assert crowded_per_region(g.cells()[0].reshape(M, M), tile + 9)[0] > 32
     assert g.validate() == (0, 0)
 
 
