@@ -16,7 +16,9 @@
 // random number is keyed by (seed, sweep, cell, trial), so the recomputed
 // halo is identical to theirs and the trajectory does not depend on TILE.
 //
-// In LDS a cell keeps its (at most 4) disks as centred offsets s = u - c,
+// In LDS a cell keeps its (at most 4) disks as centred offsets s = u - c
+// (four slots per record, or two with a side table for the rare fuller
+// cells),
 // c = floor(W/2) q, so |s| <= w/2 and, for a trial position s' and a
 // neighbour cell at column offset di, q_di = s' - di w is exact (|q_di| < 4)
 // and dx = s_k - q_di is the exact separation whenever |dx| < 4: one
@@ -912,14 +914,13 @@ int occupancy_t() {
 
 struct Entry {
     uint32_t tile, threads;
-    bool two;  // two-slot records
     void (*fn)(const BoxView &, hipStream_t, unsigned long long *);
     void (*batch)(const BoxView *, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t,
                   hipStream_t);
     int (*occ)();
 };
 #define MPMC_SHAPE(T, N, TWO) \
-    {T, N, TWO, launch_t<T, N, TWO>, launch_batch_t<T, N, TWO>, occupancy_t<T, N, TWO>}
+    {T, N, launch_t<T, N, TWO>, launch_batch_t<T, N, TWO>, occupancy_t<T, N, TWO>}
 // The 34- and 48-cell tiles hold two-slot records: 37 KB of LDS and four
 // workgroups of 256 threads per CU, 64 KB and two of 512.  At N = 1024^2,
 // eta = 0.716 (M = 1072) the 34-cell tile gives 1024 tiles, one round.
